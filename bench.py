@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSV HMC hot path on one MI355X.
+
+One step = one sweep of the whole path over the single long series: momentum
+refresh, k leapfrog steps, dH reduction, Metropolis test, sufficient
+statistics and the theta update (rsv_hmc_sweep with n = 1 per step, the K
+steps issued as one call).  Default workload: T = 2^22 sites, theta =
+(0.97, -0.3, -0.2, 0.04, 0.09), k = 50, dtau tuned to ~80% acceptance,
+FP64, one chain, synthetic data from the model (seed 2).
+
+Prints ONE JSON line.  ``value`` is leapfrog site-updates per second of the
+whole sweep (T * k * K / elapsed).  ``roofline`` describes the trajectory
+kernel (the dominant kernel), timed with HIP events recorded by the library
+on its stream around that kernel.  ``cpu_baseline`` times the FP64 CPU oracle
+on a bounded sample of the same workload on the host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "min-ESS/s and leapfrog site-updates/s; learned-mass FP32 vs plain FP64 HMC"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+STREAM_BYTES = {"f64": 48, "f32": 24}   # read h,p,y^2,lnRV + write h,p per site-update
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--T", type=int, default=1 << 22)
+    ap.add_argument("--k", type=int, default=50)
+    ap.add_argument("--dtau", type=float, default=0.0, help="0 = tune to ~80%% acceptance")
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--sites-per-lane", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=2,
+                    help="oracle sweeps timed for cpu_baseline (0 = skip)")
+    return ap.parse_args()
+
+
+def tune_dtau(smp, k, T, first_sweep, target=0.8):
+    """Geometric search of dtau for mean min(1, exp(-dH)) ~ target over pilot
+    sweeps (theta updated, as in the measured run)."""
+    import numpy as np
+    dtau = 0.05 * (1000.0 / T) ** 0.25
+    lo, hi = None, None
+    sweep = first_sweep
+    n_pilot = 60
+    for _ in range(14):
+        out = smp.sweep(sweep, n_pilot, (k, dtau), update_theta=True, record=("delta_h",))
+        sweep += n_pilot
+        dh = out["delta_h"].cpu().numpy().ravel()
+        acc = float(np.mean(np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9)))))
+        if abs(acc - target) < 0.03:
+            break
+        if acc > target:
+            lo = dtau
+            dtau = dtau * 1.3 if hi is None else math.sqrt(dtau * hi)
+        else:
+            hi = dtau
+            dtau = dtau / 1.3 if lo is None else math.sqrt(dtau * lo)
+    return dtau, acc, sweep
+
+
+def isa_figures(precision, S):
+    path = os.path.join(ROOT, "paper_1603_08114_amd", "isa_counts.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    return table.get(f"{precision}_S{S}")
+
+
+def cpu_baseline(y, lr, h0, theta, k, dtau, n_sweeps, seed, T):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    oracle.run(h0, theta, y * y, lr, k, dtau, n_sweeps, seed=seed, update_theta=True)
+    dt = time.perf_counter() - t0
+    return {"value": T * k * n_sweeps / dt, "unit": "site-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_sweeps} sweeps (trajectory + theta update) of the same T={T} series, "
+                      f"k={k}, FP64, serial C",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1603_08114_amd import api
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+
+    T, k, K, W = args.T, args.k, args.steps, args.warmup
+    theta = dict(synth.THETA_STAR)
+    y, lr, h_true = synth.simulate_rsv_long(T, theta, args.seed)
+    prec = RSV_F64 if args.precision == "f64" else RSV_F32_MIXED
+    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
+                         precision=prec, sites_per_lane=args.sites_per_lane)
+    S = int(smp.pb.sites_per_lane) or (8 if prec == RSV_F64 else 16)
+    print(f"[bench] T={T} k={k} precision={args.precision} S={S}", file=sys.stderr, flush=True)
+
+    sweep = 0
+    if args.dtau > 0:
+        dtau = args.dtau
+    else:
+        dtau, acc_pilot, sweep = tune_dtau(smp, k, T, sweep)
+        print(f"[bench] tuned dtau={dtau:.6g} (pilot acceptance {acc_pilot:.3f})",
+              file=sys.stderr, flush=True)
+    lf = (k, dtau)
+    smp.sweep(sweep, W, lf, update_theta=True, record=())
+    sweep += W
+    torch.cuda.synchronize()
+
+    api.rsv_hmc_profile(smp.ctx, K)
+    stream = smp.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    out = smp.sweep(sweep, K, lf, update_theta=True, record=("accepted",))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    elapsed = ev0.elapsed_time(ev1) / 1e3
+    kern_ms, n_rec = api.rsv_hmc_kernel_time(smp.ctx)
+    api.rsv_hmc_profile(smp.ctx, 0)
+    acc_rate = float(out["accepted"].float().mean().item())
+    status, n_nonfinite = smp.check()
+    assert status == 0, "non-finite state after the timed run"
+
+    site_updates = float(T) * k * K
+    value = site_updates / elapsed
+    kern_avg = kern_ms / 1e3 / max(n_rec, 1)
+    traj_rate = float(T) * k / kern_avg
+    isa = isa_figures(args.precision, S)
+    peak = FP64_PEAK_TFLOPS if args.precision == "f64" else FP32_PEAK_TFLOPS
+    roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
+            "traffic": None, "kernel": "k_traj", "avg_launch_ms": kern_avg * 1e3,
+            "launches": n_rec}
+    if isa:
+        # FMA-equivalent rate of the kernel's VALU issue: 2 x (VALU instructions per
+        # site-update in the leapfrog loop, from the ISA) x site-updates / s.
+        per_unit = 2.0 * isa["valu_per_site_update"]
+        roof["achieved"] = per_unit * traj_rate / 1e12
+        roof["frac"] = roof["achieved"] / peak
+        roof["flop_per_site_update"] = per_unit
+    stream_gbs = STREAM_BYTES[args.precision] * traj_rate / 1e9
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+        "config": {"workload": f"single-series RSV HMC sweep, T={T}, k={k}, "
+                               f"{args.precision.upper()}, theta updated every sweep",
+                   "T": T, "k": k, "dtau": dtau, "chains": 1, "sites_per_lane": S},
+        "roofline": roof,
+        "acceptance": acc_rate,
+        "traj_kernel_site_updates_per_s": traj_rate,
+        "streaming_equivalent": {"bytes_per_site_update": STREAM_BYTES[args.precision],
+                                 "GB/s": stream_gbs, "frac_of_hbm_peak": stream_gbs / HBM_PEAK_GBS},
+        "wall_s": wall,
+    }
+    if args.cpu_sweeps > 0:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(y, lr, h_true, theta, k, dtau, args.cpu_sweeps,
+                                           args.seed, T)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * rsv_hmc.h -- C ABI of the MI355X (gfx950) HIP library for the Hybrid Monte
+ * Carlo volatility update of the realized stochastic volatility (RSV) model.
+ *
+ * Paper: T. Takaishi, "GPU Computing in Bayesian Inference of Realized
+ * Stochastic Volatility Model", arXiv:1603.08114.
+ *   Sec. 2, eqs. (1)-(3)  the RSV model: y_t = exp(h_t/2) eps_t,
+ *                         ln RV_t = xi + h_t + u_t,
+ *                         h_{t+1} = mu + phi (h_t - mu) + eta_t;
+ *                         theta = (phi, mu, xi, sigma_eta^2, sigma_u^2).
+ *   Sec. 3, eqs. (4)-(5)  Hamilton's equations, H = 1/2 sum p^2 - ln f(h,theta).
+ *   Sec. 3, eqs. (6)-(8)  second-order leapfrog (h half step, p full step,
+ *                         h half step), repeated k times, l = k dtau.
+ *   Sec. 3 (end)          Metropolis test, accept with min{1, exp(-dH)}.
+ *   Sec. 5, eqs. (9)-(11) the same step applied to all sites i = 1..T in
+ *                         parallel (here fused, and blocked in time).
+ *
+ * Conventions for every entry point
+ *   - Sites are 0-based: site t here is the paper's t+1.
+ *   - "device" pointers are HIP device memory owned by the caller (the
+ *     Python binding passes torch tensors).  The library never allocates or
+ *     frees device memory; it works inside the caller's workspace.
+ *   - "host" pointers are read during the call only.
+ *   - All work is enqueued on the stream given to rsv_hmc_init; calls other
+ *     than init, rsv_hmc_check and destroy do not synchronise.
+ *   - A non-OK status leaves the context usable; rsv_last_error() returns a
+ *     thread-local message describing the most recent failure.
+ *   - One context per stream; a context is not thread-safe.
+ *
+ * Data layout (HBM)
+ *   Series s = 0..S-1 has T_s = offsets[s+1] - offsets[s] sites; its data
+ *   y, log_rv occupy [offsets[s], offsets[s+1]) of the data arrays.
+ *   Chain c = s*C + j (j = 0..C-1) has its state h at
+ *   [C*offsets[s] + j*T_s, C*offsets[s] + (j+1)*T_s) of the state array:
+ *   every chain is one contiguous run of sites, chains of a series adjacent.
+ *   theta is one rsv_theta per chain (array of structs, 40 bytes each).
+ */
+#ifndef RSV_HMC_H
+#define RSV_HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rsv_status;
+enum {
+    RSV_OK = 0,
+    RSV_EINVAL = -1,     /* an argument or the problem is invalid           */
+    RSV_EDEVICE = -2,    /* a HIP call failed                               */
+    RSV_ENOMEM = -3,     /* the workspace is too small                      */
+    RSV_ESTATE = -4,     /* call out of order (e.g. context not initialised) */
+    RSV_ENONFINITE = -5  /* non-finite state or data was detected           */
+};
+
+/* Arithmetic of the leapfrog.  RSV_F64: everything in FP64.
+ * RSV_F32_MIXED: h, p and the force in FP32; dH, the Metropolis log-ratio,
+ * the sufficient statistics and theta in FP64. */
+typedef enum { RSV_F64 = 0, RSV_F32_MIXED = 1 } rsv_precision;
+
+/* Model terms of -ln f.  Both on = the RSV model of eqs. (1)-(3).  Without
+ * RSV_TERM_RETURN (eq. (1)) the model is linear-Gaussian; without
+ * RSV_TERM_RV (eq. (2)) it is the plain SV model and xi, sigma_u^2 are not
+ * updated. */
+enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
+
+/* theta of Sec. 2. */
+typedef struct { double phi, mu, xi, sig2_eta, sig2_u; } rsv_theta;
+
+/* Priors of the theta update.  The paper states none; the reading taken is
+ * phi ~ U(-1,1), mu ~ N(mu_mean, mu_var), xi ~ N(xi_mean, xi_var),
+ * sigma_eta^2 ~ IG(eta_shape, eta_scale), sigma_u^2 ~ IG(u_shape, u_scale). */
+typedef struct {
+    double mu_mean, mu_var, xi_mean, xi_var;
+    double eta_shape, eta_scale, u_shape, u_scale;
+} rsv_prior;
+
+/* Leapfrog knobs of Sec. 3: k steps of size dtau. */
+typedef struct { int32_t n_steps; int32_t reserved; double dtau; } rsv_leapfrog;
+
+typedef struct {
+    int32_t n_series;           /* S >= 1                                      */
+    int32_t chains_per_series;  /* C >= 1                                      */
+    const int64_t *offsets;     /* host, S+1 entries, offsets[0] = 0,
+                                   T_s = offsets[s+1]-offsets[s] >= 3          */
+    const double *y;            /* device, offsets[S] daily returns y_t        */
+    const double *log_rv;       /* device, offsets[S] values ln RV_t           */
+    int32_t precision;          /* rsv_precision                               */
+    int32_t terms;              /* RSV_TERM_* bit set, at least one bit        */
+    int32_t max_steps;          /* largest k any later call will use (>= 1)    */
+    int32_t sites_per_lane;     /* tile shape of the trajectory kernel: sites
+                                   held by each lane (0 = library default;
+                                   RSV_F64: 8 or 16, RSV_F32_MIXED: 16 or 32);
+                                   a wavefront integrates 64 * sites_per_lane
+                                   sites, of which all but a k+1 halo on each
+                                   cut side are exact                          */
+    uint64_t seed;              /* key of all random streams                   */
+    rsv_prior prior;
+} rsv_problem;
+
+/* Per-sweep records written by rsv_hmc_sweep.  Every pointer may be NULL. */
+typedef struct {
+    double *delta_h;     /* device, n_sweeps * n_chains, dH of each trajectory */
+    int32_t *accepted;   /* device, n_sweeps * n_chains, 1 if accepted         */
+    rsv_theta *theta;    /* device, n_sweeps * n_chains, theta after the sweep */
+    void *h;             /* device, n_sweeps * n_state, h after the sweep, in the
+                            state precision (FP64 or FP32)                      */
+} rsv_trace;
+
+typedef struct rsv_ctx rsv_ctx;
+
+/* Bytes of device workspace rsv_hmc_init needs for this problem (0 if the
+ * problem is invalid; see rsv_last_error). */
+size_t rsv_hmc_workspace_bytes(const rsv_problem *pb);
+
+/* Number of state entries, C * offsets[S] (0 if invalid). */
+int64_t rsv_hmc_state_size(const rsv_problem *pb);
+
+/* Create a context.
+ *   h        device, rsv_hmc_state_size entries of double (RSV_F64) or float
+ *            (RSV_F32_MIXED): the initial h on entry; the library keeps the
+ *            current state of every chain here after each call.
+ *   theta    device, S*C rsv_theta, initial values; updated in place.
+ *   log_mass device, offsets[S] floats: log of the diagonal mass m_t of each
+ *            series-site (shared by the chains of a series), or NULL for
+ *            m = 1 (the paper's kinetic term 1/2 sum p^2).
+ *   workspace, ws_bytes  device scratch of at least rsv_hmc_workspace_bytes.
+ *   hip_stream  hipStream_t to enqueue on (NULL = the null stream).
+ * Validates the problem on the host and the data, h and theta on the device
+ * (one synchronisation): RSV_EINVAL for T_s < 3, non-finite y / log_rv / h,
+ * |phi| >= 1, a variance <= 0 or a bad prior; RSV_ENOMEM if ws_bytes is too
+ * small.  The pointers are borrowed and must outlive the context. */
+rsv_status rsv_hmc_init(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta *theta,
+                        const float *log_mass, void *workspace, size_t ws_bytes,
+                        void *hip_stream);
+
+/* Momentum refresh of sweep `sweep` (the Gibbs draw p ~ N(0, m) implied by
+ * the kinetic term of H, Sec. 3), written to p_out (device, FP64, one entry
+ * per state entry).  The trajectory of that sweep starts from exactly these
+ * momenta (rounded to FP32 on the mixed path). */
+rsv_status rsv_hmc_momenta(rsv_ctx *c, uint64_t sweep, double *p_out);
+
+/* One HMC trajectory for every chain (Sec. 3): momentum refresh, k leapfrog
+ * steps of eqs. (6)-(8), dH = H(p',h') - H(p,h) as a compensated FP64 sum
+ * of per-site differences, and the Metropolis test accept iff
+ * ln u < -dH (a non-finite dH rejects).  On acceptance the chain's state
+ * becomes h', else it stays.  theta is not changed.
+ *   lf       host, one rsv_leapfrog per series (k <= max_steps, dtau > 0).
+ *   p0       device FP64 momenta overriding the refresh, or NULL.
+ *   log_u    device FP64 per chain overriding ln u, or NULL.
+ *   delta_h  device FP64 per chain, or NULL.   accepted: device int32 per
+ *            chain, or NULL. */
+rsv_status rsv_hmc_trajectory(rsv_ctx *c, uint64_t sweep, const rsv_leapfrog *lf,
+                              const double *p0, const double *log_u,
+                              double *delta_h, int32_t *accepted);
+
+/* theta update of every chain from the current h (the paper's parameter
+ * estimation by MCMC, Sec. 2; the sampler is a reading): Gibbs sweep
+ * mu -> phi (independence Metropolis) -> sigma_eta^2 -> xi -> sigma_u^2,
+ * each conditional formed from sufficient statistics of h reduced on the
+ * GPU in FP64.
+ *   suff_stats  device FP64, 7 per chain {B, B2, BB, D1, D2, b_first, b_last}
+ *               with b_t = h_t - mu, e_t = ln RV_t - h_t - xi (theta before
+ *               the update): B = sum b, B2 = sum b^2, BB = sum b_t b_{t+1},
+ *               D1 = sum e, D2 = sum e^2; or NULL. */
+rsv_status rsv_theta_update(rsv_ctx *c, uint64_t sweep, double *suff_stats);
+
+/* n_sweeps sweeps, each one trajectory (as rsv_hmc_trajectory, streams of
+ * sweep first_sweep + i) followed, if update_theta, by the theta update (as
+ * rsv_theta_update).  trace (host struct of device pointers) may be NULL. */
+rsv_status rsv_hmc_sweep(rsv_ctx *c, uint64_t first_sweep, int32_t n_sweeps,
+                         const rsv_leapfrog *lf, int32_t update_theta,
+                         const rsv_trace *trace);
+
+/* Synchronise the stream and report device-side events since the last
+ * check: *n_nonfinite (may be NULL) receives the number of trajectories
+ * whose dH was not finite.  Returns RSV_ENONFINITE if the current state of
+ * any chain holds a non-finite value, else RSV_OK. */
+rsv_status rsv_hmc_check(rsv_ctx *c, int64_t *n_nonfinite);
+
+/* Kernel timing (measurement support).  rsv_hmc_profile allocates
+ * max_records pairs of HIP events (0 frees them); while records remain, each
+ * later trajectory (in rsv_hmc_trajectory or one sweep of rsv_hmc_sweep) is
+ * bracketed by a pair recorded on the context's stream around the
+ * trajectory kernels only.  rsv_hmc_kernel_time waits for the last record,
+ * returns the summed milliseconds and the number of records, and starts a
+ * new series of records. */
+rsv_status rsv_hmc_profile(rsv_ctx *c, int32_t max_records);
+rsv_status rsv_hmc_kernel_time(rsv_ctx *c, double *total_ms, int64_t *n_records);
+
+/* Free the host context (device memory stays the caller's). */
+rsv_status rsv_hmc_destroy(rsv_ctx *c);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char *rsv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,556 @@
+// rsv_capi.hip -- host side of the C ABI declared in include/rsv_hmc.h.
+//
+// Owns no device memory: carves the caller's workspace, builds the tile
+// decomposition of every chain on the host (re-built only when the leapfrog
+// knobs change), and enqueues the kernels of rsv_kernels.hip on the caller's
+// stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rsv_hmc.h"
+#include "rsv_internal.h"
+
+using namespace rsv;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rsv_status fail(rsv_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define RSV_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) return fail(RSV_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int halo_for(int n_steps) { return (n_steps + 1 + 3) & ~3; }
+
+// Tile decomposition of one chain of length T for S sites per lane and a
+// trajectory of n_steps: tiles of 64*S loaded sites whose exact ranges
+// [a, b) partition [0, T).  Returns false if the halo does not fit.
+bool tile_chain(int32_t chain, int32_t T, int S, int n_steps, std::vector<TileDesc>& body,
+                std::vector<TileDesc>& edges) {
+    const int L = 64 * S;
+    const int H = halo_for(n_steps);
+    if (T <= L) {
+        const TileDesc t{chain, 0, 0, T};
+        if (T % S != 0) edges.push_back(t); else body.push_back(t);
+        return true;
+    }
+    if (L <= 2 * H) return false;
+    int32_t a = 0, b = L - H;
+    body.push_back(TileDesc{chain, 0, a, b});
+    for (;;) {
+        a = b;
+        const int32_t la = a - H;
+        if (la + L >= T) {
+            const TileDesc t{chain, la, a, T};
+            if ((T - la) % S != 0) edges.push_back(t); else body.push_back(t);
+            return true;
+        }
+        b = la + L - H;
+        body.push_back(TileDesc{chain, la, a, b});
+    }
+}
+
+int32_t count_tiles(int32_t T, int S, int n_steps) {
+    std::vector<TileDesc> b, e;
+    if (!tile_chain(0, T, S, n_steps, b, e)) return -1;
+    return static_cast<int32_t>(b.size() + e.size());
+}
+
+struct Layout {
+    size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
+           edge = 0, accept = 0, counters = 0, total = 0;
+    int32_t max_tiles = 0;
+};
+
+rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_state) {
+    if (!pb) return fail(RSV_EINVAL, "problem is NULL");
+    if (pb->n_series < 1) return fail(RSV_EINVAL, "n_series must be >= 1");
+    if (pb->chains_per_series < 1) return fail(RSV_EINVAL, "chains_per_series must be >= 1");
+    const int64_t n_chains = static_cast<int64_t>(pb->n_series) * pb->chains_per_series;
+    if (n_chains > 65535) return fail(RSV_EINVAL, "at most 65535 chains");
+    if (!pb->offsets) return fail(RSV_EINVAL, "offsets is NULL");
+    if (pb->offsets[0] != 0) return fail(RSV_EINVAL, "offsets[0] must be 0");
+    for (int s = 0; s < pb->n_series; ++s) {
+        const int64_t T = pb->offsets[s + 1] - pb->offsets[s];
+        if (T < 3) return fail(RSV_EINVAL, "series %d has T = %lld < 3", s, (long long)T);
+        if (T > (int64_t(1) << 30)) return fail(RSV_EINVAL, "series %d is too long", s);
+    }
+    if (pb->precision != RSV_F64 && pb->precision != RSV_F32_MIXED)
+        return fail(RSV_EINVAL, "unknown precision %d", pb->precision);
+    if (pb->terms < 1 || pb->terms > RSV_TERMS_RSV)
+        return fail(RSV_EINVAL, "terms must be a non-empty subset of RSV_TERMS_RSV");
+    if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
+    const rsv_prior& p = pb->prior;
+    if (!(p.mu_var > 0 && p.xi_var > 0 && p.eta_shape > 0 && p.eta_scale > 0 && p.u_shape > 0 &&
+          p.u_scale > 0 && std::isfinite(p.mu_mean) && std::isfinite(p.xi_mean) &&
+          std::isfinite(p.mu_var) && std::isfinite(p.xi_var)))
+        return fail(RSV_EINVAL, "prior variances, shapes and scales must be finite and > 0");
+    *n_data = pb->offsets[pb->n_series];
+    *n_state = *n_data * pb->chains_per_series;
+    return RSV_OK;
+}
+
+rsv_status make_layout(const rsv_problem* pb, Layout* L) {
+    int64_t n_data = 0, n_state = 0;
+    rsv_status st = check_problem(pb, &n_data, &n_state);
+    if (st != RSV_OK) return st;
+    const int S = traj_sites_per_lane(pb->precision, pb->sites_per_lane);
+    if (S < 0) return fail(RSV_EINVAL, "sites_per_lane = %d is not available for this precision",
+                           pb->sites_per_lane);
+    int64_t tiles = 0;
+    for (int s = 0; s < pb->n_series; ++s) {
+        const int32_t T = static_cast<int32_t>(pb->offsets[s + 1] - pb->offsets[s]);
+        const int32_t n = count_tiles(T, S, pb->max_steps);
+        if (n < 0)
+            return fail(RSV_EINVAL, "max_steps = %d needs a halo wider than a tile (%d sites)",
+                        pb->max_steps, 64 * S);
+        tiles += static_cast<int64_t>(n) * pb->chains_per_series;
+    }
+    if (tiles > (int64_t(1) << 30)) return fail(RSV_EINVAL, "too many tiles");
+    const int64_t n_chains = static_cast<int64_t>(pb->n_series) * pb->chains_per_series;
+    const size_t elem = pb->precision == RSV_F64 ? sizeof(double) : sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L->y2_d = take(n_data * sizeof(double));
+    if (pb->precision == RSV_F32_MIXED) {
+        L->y2_f = take(n_data * sizeof(float));
+        L->lrv_f = take(n_data * sizeof(float));
+    }
+    L->h_prop = take(n_state * elem);
+    L->tiles = take(tiles * sizeof(TileDesc));
+    L->chains = take(n_chains * sizeof(ChainDesc));
+    L->partials = take(tiles * kPart * sizeof(double));
+    L->edge = take(n_chains * kEdge * sizeof(double));
+    L->accept = take(n_chains * sizeof(int32_t));
+    L->counters = take(kNumCounters * sizeof(uint32_t));
+    L->total = off;
+    L->max_tiles = static_cast<int32_t>(tiles);
+    return RSV_OK;
+}
+
+}  // namespace
+
+struct rsv_ctx {
+    rsv_problem pb;
+    std::vector<int64_t> offsets;
+    int32_t n_chains = 0, C = 0, S = 0, max_T = 0;
+    int64_t n_data = 0, n_state = 0;
+    void* h = nullptr;
+    rsv_theta* theta = nullptr;
+    const float* log_mass = nullptr;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    Layout lay;
+    // device views into the workspace
+    double* y2_d = nullptr;
+    float* y2_f = nullptr;
+    float* lrv_f = nullptr;
+    void* h_prop = nullptr;
+    TileDesc* tiles = nullptr;
+    ChainDesc* chains = nullptr;
+    double* partials = nullptr;
+    double* edge = nullptr;
+    int32_t* accept = nullptr;
+    uint32_t* counters = nullptr;
+    // host mirrors of the current decomposition
+    std::vector<rsv_leapfrog> lf;
+    std::vector<TileDesc> h_tiles;
+    std::vector<ChainDesc> h_chains;
+    int32_t n_body = 0, n_edge = 0;
+    // kernel timing: event pairs around each trajectory-kernel launch
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used = 0;
+
+    ~rsv_ctx() {
+        for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
+    for (int s = 0; s < c->pb.n_series; ++s) {
+        if (lf[s].n_steps < 1 || lf[s].n_steps > c->pb.max_steps)
+            return fail(RSV_EINVAL, "series %d: n_steps %d outside [1, max_steps = %d]", s,
+                        lf[s].n_steps, c->pb.max_steps);
+        if (!(lf[s].dtau > 0.0) || !std::isfinite(lf[s].dtau))
+            return fail(RSV_EINVAL, "series %d: dtau must be finite and > 0", s);
+    }
+    std::vector<TileDesc> body, edges;
+    std::vector<ChainDesc> chains(c->n_chains);
+    std::vector<int32_t> edge_of(c->n_chains, -1);
+    for (int s = 0; s < c->pb.n_series; ++s) {
+        const int32_t T = static_cast<int32_t>(c->offsets[s + 1] - c->offsets[s]);
+        for (int j = 0; j < c->C; ++j) {
+            const int32_t ch = s * c->C + j;
+            ChainDesc& d = chains[ch];
+            d.h_off = c->C * c->offsets[s] + static_cast<int64_t>(j) * T;
+            d.d_off = c->offsets[s];
+            d.T = T;
+            d.series = s;
+            d.tile_begin = static_cast<int32_t>(body.size());
+            const size_t n_edge_before = edges.size();
+            if (!tile_chain(ch, T, c->S, lf[s].n_steps, body, edges))
+                return fail(RSV_EINVAL, "series %d: n_steps %d too large for a tile", s,
+                            lf[s].n_steps);
+            d.tile_count = static_cast<int32_t>(body.size()) - d.tile_begin;
+            if (edges.size() > n_edge_before) edge_of[ch] = static_cast<int32_t>(n_edge_before);
+            d.n_steps = lf[s].n_steps;
+            d.dtau = lf[s].dtau;
+        }
+    }
+    const int32_t n_total = static_cast<int32_t>(body.size() + edges.size());
+    if (n_total > c->lay.max_tiles) return fail(RSV_ENOMEM, "tile count exceeds the workspace");
+    for (int32_t ch = 0; ch < c->n_chains; ++ch)
+        chains[ch].edge_tile = edge_of[ch] < 0 ? -1 : static_cast<int32_t>(body.size()) + edge_of[ch];
+    c->n_body = static_cast<int32_t>(body.size());
+    c->n_edge = static_cast<int32_t>(edges.size());
+    c->h_tiles = body;
+    c->h_tiles.insert(c->h_tiles.end(), edges.begin(), edges.end());
+    c->h_chains = chains;
+    RSV_HIP(hipMemcpyAsync(c->tiles, c->h_tiles.data(), c->h_tiles.size() * sizeof(TileDesc),
+                           hipMemcpyHostToDevice, c->stream));
+    RSV_HIP(hipMemcpyAsync(c->chains, c->h_chains.data(), c->h_chains.size() * sizeof(ChainDesc),
+                           hipMemcpyHostToDevice, c->stream));
+    RSV_HIP(hipStreamSynchronize(c->stream));
+    c->lf.assign(lf, lf + c->pb.n_series);
+    return RSV_OK;
+}
+
+rsv_status ensure_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
+    if (!lf) return fail(RSV_EINVAL, "leapfrog parameters are NULL");
+    bool same = c->lf.size() == static_cast<size_t>(c->pb.n_series);
+    for (int s = 0; same && s < c->pb.n_series; ++s)
+        same = c->lf[s].n_steps == lf[s].n_steps && c->lf[s].dtau == lf[s].dtau;
+    return same ? RSV_OK : build_tiles(c, lf);
+}
+
+template <typename R>
+TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
+    TrajArgs<R> a;
+    a.tiles = c->tiles;
+    a.tile_first = 0;
+    a.n_list = 0;
+    a.chains = c->chains;
+    a.theta = c->theta;
+    a.h_cur = static_cast<const R*>(c->h);
+    a.h_prop = static_cast<R*>(c->h_prop);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        a.y2 = reinterpret_cast<const R*>(c->y2_d);
+        a.lrv = reinterpret_cast<const R*>(c->pb.log_rv);
+    } else {
+        a.y2 = reinterpret_cast<const R*>(c->y2_f);
+        a.lrv = reinterpret_cast<const R*>(c->lrv_f);
+    }
+    a.y2_d = c->y2_d;
+    a.lrv_d = c->pb.log_rv;
+    a.log_mass = c->log_mass;
+    a.p0 = p0;
+    a.seed = c->pb.seed;
+    a.sweep = sweep;
+    a.partials = c->partials;
+    a.chain_edge = c->edge;
+    a.terms = c->pb.terms;
+    return a;
+}
+
+template <typename R>
+rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0) {
+    TrajArgs<R> a = traj_args<R>(c, sweep, p0);
+    const bool mass = c->log_mass != nullptr;
+    const bool timed = c->ev_used < c->ev_start.size();
+    if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
+    a.tile_first = 0;
+    a.n_list = c->n_body;
+    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, mass, false, &a));
+    a.tile_first = c->n_body;
+    a.n_list = c->n_edge;
+    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, mass, true, &a));
+    if (timed) RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used++], c->stream));
+    return RSV_OK;
+}
+
+rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
+                          double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
+                          void* h_trace, double* stats_out) {
+    const rsv_status st = c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0)
+                                                     : launch_traj_all<float>(c, sweep, p0);
+    if (st != RSV_OK) return st;
+    FinalizeArgs f;
+    f.chains = c->chains;
+    f.n_chains = c->n_chains;
+    f.partials = c->partials;
+    f.chain_edge = c->edge;
+    f.theta = c->theta;
+    f.prior = c->pb.prior;
+    f.seed = c->pb.seed;
+    f.sweep = sweep;
+    f.terms = c->pb.terms;
+    f.do_metropolis = 1;
+    f.do_theta = do_theta;
+    f.log_u = log_u;
+    f.accept_ws = c->accept;
+    f.delta_h_out = delta_h;
+    f.accepted_out = accepted;
+    f.theta_trace = theta_trace;
+    f.stats_out = stats_out;
+    f.counters = c->counters;
+    RSV_HIP(launch_finalize(c->stream, f));
+    RSV_HIP(launch_commit(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h_prop, c->h,
+                          h_trace, c->pb.precision));
+    return RSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsv_last_error(void) { return g_last_error.c_str(); }
+
+int64_t rsv_hmc_state_size(const rsv_problem* pb) {
+    int64_t n_data = 0, n_state = 0;
+    if (check_problem(pb, &n_data, &n_state) != RSV_OK) return 0;
+    return n_state;
+}
+
+size_t rsv_hmc_workspace_bytes(const rsv_problem* pb) {
+    Layout L;
+    if (make_layout(pb, &L) != RSV_OK) return 0;
+    return L.total;
+}
+
+rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
+                        const float* log_mass, void* workspace, size_t ws_bytes,
+                        void* hip_stream) {
+    if (!out) return fail(RSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    rsv_status st = make_layout(pb, &L);
+    if (st != RSV_OK) return st;
+    if (!pb->y || !pb->log_rv || !h || !theta || !workspace)
+        return fail(RSV_EINVAL, "y, log_rv, h, theta and workspace must be non-NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(RSV_EINVAL, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < L.total)
+        return fail(RSV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    rsv_ctx* c = new rsv_ctx();
+    c->pb = *pb;
+    c->offsets.assign(pb->offsets, pb->offsets + pb->n_series + 1);
+    c->pb.offsets = c->offsets.data();
+    c->C = pb->chains_per_series;
+    c->n_chains = pb->n_series * pb->chains_per_series;
+    c->S = traj_sites_per_lane(pb->precision, pb->sites_per_lane);
+    c->n_data = c->offsets[pb->n_series];
+    c->n_state = c->n_data * c->C;
+    for (int s = 0; s < pb->n_series; ++s)
+        c->max_T = std::max<int32_t>(c->max_T, static_cast<int32_t>(c->offsets[s + 1] - c->offsets[s]));
+    c->h = h;
+    c->theta = theta;
+    c->log_mass = log_mass;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char*>(workspace);
+    c->lay = L;
+    c->y2_d = reinterpret_cast<double*>(c->ws + L.y2_d);
+    if (pb->precision == RSV_F32_MIXED) {
+        c->y2_f = reinterpret_cast<float*>(c->ws + L.y2_f);
+        c->lrv_f = reinterpret_cast<float*>(c->ws + L.lrv_f);
+    }
+    c->h_prop = c->ws + L.h_prop;
+    c->tiles = reinterpret_cast<TileDesc*>(c->ws + L.tiles);
+    c->chains = reinterpret_cast<ChainDesc*>(c->ws + L.chains);
+    c->partials = reinterpret_cast<double*>(c->ws + L.partials);
+    c->edge = reinterpret_cast<double*>(c->ws + L.edge);
+    c->accept = reinterpret_cast<int32_t*>(c->ws + L.accept);
+    c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
+
+    auto bail = [&](rsv_status s) {
+        delete c;
+        return s;
+    };
+#define RSV_HIP_INIT(call)                                                               \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return bail(fail(RSV_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)));      \
+    } while (0)
+
+    RSV_HIP_INIT(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(uint32_t), c->stream));
+    RSV_HIP_INIT(hipMemsetAsync(c->edge, 0, c->n_chains * kEdge * sizeof(double), c->stream));
+    RSV_HIP_INIT(launch_prepare(c->stream, pb->y, pb->log_rv, c->n_data, c->y2_d, c->y2_f,
+                                c->lrv_f));
+    RSV_HIP_INIT(launch_validate(c->stream, pb->y, pb->log_rv, c->n_data, h, c->n_state,
+                                 pb->precision, c->counters));
+    std::vector<rsv_theta> th(c->n_chains);
+    RSV_HIP_INIT(hipMemcpyAsync(th.data(), theta, th.size() * sizeof(rsv_theta),
+                                hipMemcpyDeviceToHost, c->stream));
+    uint32_t cnt[kNumCounters];
+    RSV_HIP_INIT(hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    RSV_HIP_INIT(hipStreamSynchronize(c->stream));
+    if (cnt[kCntNonfiniteData])
+        return bail(fail(RSV_EINVAL, "%u non-finite values in y / log_rv", cnt[kCntNonfiniteData]));
+    if (cnt[kCntNonfiniteState])
+        return bail(fail(RSV_EINVAL, "%u non-finite values in h", cnt[kCntNonfiniteState]));
+    for (int32_t i = 0; i < c->n_chains; ++i) {
+        const rsv_theta& t = th[i];
+        if (!(std::fabs(t.phi) < 1.0) || !(t.sig2_eta > 0.0) || !(t.sig2_u > 0.0) ||
+            !std::isfinite(t.mu) || !std::isfinite(t.xi) || !std::isfinite(t.sig2_eta) ||
+            !std::isfinite(t.sig2_u))
+            return bail(fail(RSV_EINVAL, "chain %d: theta needs |phi| < 1, finite mu, xi and "
+                                         "variances > 0", i));
+    }
+    // an initial decomposition so that the theta update works before any trajectory
+    std::vector<rsv_leapfrog> lf0(pb->n_series, rsv_leapfrog{pb->max_steps, 0, 1.0});
+    st = build_tiles(c, lf0.data());
+    if (st != RSV_OK) return bail(st);
+#undef RSV_HIP_INIT
+    *out = c;
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (!p_out) return fail(RSV_EINVAL, "p_out is NULL");
+    RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T, c->log_mass, c->pb.seed,
+                           sweep, p_out));
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf,
+                              const double* p0, const double* log_u, double* delta_h,
+                              int32_t* accepted) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    rsv_status st = ensure_tiles(c, lf);
+    if (st != RSV_OK) return st;
+    return run_trajectory(c, sweep, p0, log_u, delta_h, accepted, 0, nullptr, nullptr, nullptr);
+}
+
+rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
+                         c->pb.log_rv, c->partials, c->edge, c->pb.precision));
+    FinalizeArgs f;
+    f.chains = c->chains;
+    f.n_chains = c->n_chains;
+    f.partials = c->partials;
+    f.chain_edge = c->edge;
+    f.theta = c->theta;
+    f.prior = c->pb.prior;
+    f.seed = c->pb.seed;
+    f.sweep = sweep;
+    f.terms = c->pb.terms;
+    f.do_metropolis = 0;
+    f.do_theta = 1;
+    f.log_u = nullptr;
+    f.accept_ws = c->accept;
+    f.delta_h_out = nullptr;
+    f.accepted_out = nullptr;
+    f.theta_trace = nullptr;
+    f.stats_out = suff_stats;
+    f.counters = c->counters;
+    RSV_HIP(launch_finalize(c->stream, f));
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
+                         const rsv_leapfrog* lf, int32_t update_theta, const rsv_trace* trace) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (n_sweeps < 0) return fail(RSV_EINVAL, "n_sweeps must be >= 0");
+    rsv_status st = ensure_tiles(c, lf);
+    if (st != RSV_OK) return st;
+    const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
+    for (int32_t i = 0; i < n_sweeps; ++i) {
+        const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;
+        double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
+        int32_t* ac = (trace && trace->accepted) ? trace->accepted + ofs : nullptr;
+        rsv_theta* tt = (trace && trace->theta) ? trace->theta + ofs : nullptr;
+        void* ht = (trace && trace->h)
+                       ? static_cast<char*>(trace->h) + static_cast<size_t>(i) * c->n_state * elem
+                       : nullptr;
+        st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
+                            update_theta ? 1 : 0, tt, ht, nullptr);
+        if (st != RSV_OK) return st;
+    }
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_check(rsv_ctx* c, int64_t* n_nonfinite) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    RSV_HIP(hipMemsetAsync(c->counters + kCntNonfiniteState, 0, sizeof(uint32_t), c->stream));
+    RSV_HIP(launch_count_nonfinite(c->stream, c->h, c->n_state, c->pb.precision,
+                                   c->counters + kCntNonfiniteState));
+    uint32_t cnt[kNumCounters];
+    RSV_HIP(hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    RSV_HIP(hipStreamSynchronize(c->stream));
+    RSV_HIP(hipMemsetAsync(c->counters + kCntNonfiniteDH, 0, sizeof(uint32_t), c->stream));
+    if (n_nonfinite) *n_nonfinite = cnt[kCntNonfiniteDH];
+    if (cnt[kCntNonfiniteState])
+        return fail(RSV_ENONFINITE, "%u non-finite values in the state", cnt[kCntNonfiniteState]);
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_profile(rsv_ctx* c, int32_t max_records) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (max_records < 0) return fail(RSV_EINVAL, "max_records must be >= 0");
+    for (hipEvent_t e : c->ev_start) RSV_HIP(hipEventDestroy(e));
+    for (hipEvent_t e : c->ev_stop) RSV_HIP(hipEventDestroy(e));
+    c->ev_start.clear();
+    c->ev_stop.clear();
+    c->ev_used = 0;
+    for (int32_t i = 0; i < max_records; ++i) {
+        hipEvent_t a, b;
+        RSV_HIP(hipEventCreate(&a));
+        RSV_HIP(hipEventCreate(&b));
+        c->ev_start.push_back(a);
+        c->ev_stop.push_back(b);
+    }
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_kernel_time(rsv_ctx* c, double* total_ms, int64_t* n_records) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    double sum = 0.0;
+    if (c->ev_used > 0) RSV_HIP(hipEventSynchronize(c->ev_stop[c->ev_used - 1]));
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float ms = 0.f;
+        RSV_HIP(hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]));
+        sum += ms;
+    }
+    if (total_ms) *total_ms = sum;
+    if (n_records) *n_records = static_cast<int64_t>(c->ev_used);
+    c->ev_used = 0;
+    return RSV_OK;
+}
+
+rsv_status rsv_hmc_destroy(rsv_ctx* c) {
+    delete c;
+    return RSV_OK;
+}
+
+}  // extern "C"

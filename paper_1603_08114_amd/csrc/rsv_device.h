@@ -1,0 +1,156 @@
+// rsv_device.h -- device building blocks of the RSV HMC library (gfx950).
+//
+// Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11),
+// Box-Muller normals, wavefront neighbour shifts by DPP, and wavefront
+// reductions.  Written for 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsv {
+
+constexpr int kWave = 64;
+
+// Stream tags (word 3 of the Philox counter): one stream per use.
+enum : uint64_t { kTagMomentum = 0, kTagAccept = 1, kTagTheta = 2 };
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10: ten rounds; each round multiplies words 0 and 2 by the two
+// round multipliers (full 128-bit products), swaps and xors with the key;
+// the key advances by the two Weyl constants after every round.
+// ---------------------------------------------------------------------------
+struct Philox4x64 {
+    uint64_t w[4];
+
+    __device__ static Philox4x64 encrypt(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                         uint64_t k0, uint64_t k1) {
+        const uint64_t mul_a = 0xD2E7470EE14C6C93ull;
+        const uint64_t mul_b = 0xCA5A826395121157ull;
+        const uint64_t weyl_a = 0x9E3779B97F4A7C15ull;
+        const uint64_t weyl_b = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+        for (int round = 0; round < 10; ++round) {
+            const uint64_t hi_a = __umul64hi(mul_a, c0), lo_a = mul_a * c0;
+            const uint64_t hi_b = __umul64hi(mul_b, c2), lo_b = mul_b * c2;
+            const uint64_t n0 = hi_b ^ c1 ^ k0;
+            const uint64_t n2 = hi_a ^ c3 ^ k1;
+            c0 = n0;
+            c1 = lo_b;
+            c2 = n2;
+            c3 = lo_a;
+            k0 += weyl_a;
+            k1 += weyl_b;
+        }
+        Philox4x64 r;
+        r.w[0] = c0; r.w[1] = c1; r.w[2] = c2; r.w[3] = c3;
+        return r;
+    }
+};
+
+// Top 52 bits of a word, centred in their cell: exact, strictly inside (0,1).
+__device__ inline double unit_open(uint64_t bits) {
+    return (static_cast<double>(bits >> 12) + 0.5) * 0x1p-52;
+}
+
+// Four uniforms of block `idx` of stream (sweep, chain, tag) under key (seed, 0).
+__device__ inline void uniforms4(uint64_t seed, uint64_t idx, uint64_t sweep, uint64_t chain,
+                                 uint64_t tag, double u[4]) {
+    const Philox4x64 x = Philox4x64::encrypt(idx, sweep, chain, tag, seed, 0ull);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = unit_open(x.w[i]);
+}
+
+// Box-Muller on one pair: radius sqrt(-2 ln u0), angle 2 pi u1.
+__device__ inline void gauss_pair(double u0, double u1, double& z0, double& z1) {
+    const double radius = sqrt(-2.0 * log(u0));
+    double s, c;
+    sincos(6.283185307179586 * u1, &s, &c);
+    z0 = radius * c;
+    z1 = radius * s;
+}
+
+// ---------------------------------------------------------------------------
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  The lane at the
+// end that has no source receives 0.
+// ---------------------------------------------------------------------------
+__device__ inline int dpp_from_lower(int v) {  // lane l <- lane l-1
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+}
+__device__ inline int dpp_from_upper(int v) {  // lane l <- lane l+1
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+}
+
+__device__ inline float from_lower(float v) {
+    return __builtin_bit_cast(float, dpp_from_lower(__builtin_bit_cast(int, v)));
+}
+__device__ inline float from_upper(float v) {
+    return __builtin_bit_cast(float, dpp_from_upper(__builtin_bit_cast(int, v)));
+}
+__device__ inline double from_lower(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(dpp_from_lower(static_cast<int>(b)));
+    const uint32_t hi = static_cast<uint32_t>(dpp_from_lower(static_cast<int>(b >> 32)));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ inline double from_upper(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(dpp_from_upper(static_cast<int>(b)));
+    const uint32_t hi = static_cast<uint32_t>(dpp_from_upper(static_cast<int>(b >> 32)));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
+// Compensated accumulation: (sum, error) pairs, merged by Knuth's TwoSum so
+// the merge is exact up to the final rounding and independent of magnitude
+// order.
+// ---------------------------------------------------------------------------
+struct Comp {
+    double s, c;
+};
+
+__device__ inline void comp_add(Comp& a, double x) {
+#pragma clang fp contract(off)
+    const double t = a.s + x;
+    const double bp = t - a.s;
+    const double err = (a.s - (t - bp)) + (x - bp);
+    a.s = t;
+    a.c += err;
+}
+
+__device__ inline Comp comp_merge(Comp a, Comp b) {
+#pragma clang fp contract(off)
+    const double t = a.s + b.s;
+    const double bp = t - a.s;
+    const double err = (a.s - (t - bp)) + (b.s - bp);
+    Comp r;
+    r.s = t;
+    r.c = a.c + b.c + err;
+    return r;
+}
+
+// Butterfly over the 64 lanes; every lane ends with the same total.
+__device__ inline Comp wave_comp_sum(Comp v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Comp o;
+        o.s = __shfl_xor(v.s, off, kWave);
+        o.c = __shfl_xor(v.c, off, kWave);
+        // order the pair by lane so both partners compute the same merge
+        const bool low = (threadIdx.x & off) == 0;
+        v = low ? comp_merge(v, o) : comp_merge(o, v);
+    }
+    return v;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off, kWave);
+        const bool low = (threadIdx.x & off) == 0;
+        v = low ? (v + o) : (o + v);
+    }
+    return v;
+}
+
+}  // namespace rsv

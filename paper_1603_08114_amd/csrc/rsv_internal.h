@@ -1,0 +1,110 @@
+// rsv_internal.h -- descriptors shared by the host library and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsv_hmc.h"
+
+namespace rsv {
+
+// A tile is the part of one chain that one wavefront integrates through a
+// whole trajectory.  It loads sites [la, la + 64*S) (clipped to [0, T)),
+// and after k steps the sites [a, b) are exact; the halo on either side is
+// at least k+1 sites (absent at the ends of the series).  la is a multiple
+// of 4 so that each lane's sites are whole Philox blocks.
+struct TileDesc {
+    int32_t chain;
+    int32_t la;
+    int32_t a;
+    int32_t b;
+};
+
+struct ChainDesc {
+    int64_t h_off;       // state index of site 0
+    int64_t d_off;       // data index of site 0 (its series)
+    int32_t T;
+    int32_t series;
+    int32_t tile_begin;  // tiles [tile_begin, tile_begin + tile_count) ...
+    int32_t tile_count;
+    int32_t edge_tile;   // ... plus this one (-1 if none)
+    int32_t n_steps;     // leapfrog steps k
+    double dtau;
+};
+
+// Per-tile partial results (doubles): dH, then {B,B2,BB,D1,D2} of the
+// proposal h', then of the current h.  Padded to 16.
+constexpr int kPart = 16;
+constexpr int kPartDH = 0, kPartProp = 1, kPartCur = 6;
+// Per-chain edge values: b_first', b_last', b_first, b_last.
+constexpr int kEdge = 4;
+
+// Counters (uint32 each) kept in the workspace.
+enum { kCntNonfiniteDH = 0, kCntNonfiniteState = 1, kCntNonfiniteData = 2, kCntGammaExhausted = 3,
+       kNumCounters = 8 };
+
+template <typename R>
+struct TrajArgs {
+    const TileDesc* tiles;
+    int32_t tile_first;         // this launch handles tiles [tile_first, tile_first + n_list)
+    int32_t n_list;
+    const ChainDesc* chains;
+    const rsv_theta* theta;
+    const R* h_cur;
+    R* h_prop;
+    const R* y2;                // y_t^2 in R
+    const R* lrv;               // ln RV_t in R
+    const double* y2_d;         // FP64 copies for dH and the statistics
+    const double* lrv_d;
+    const float* log_mass;      // per data site or nullptr
+    const double* p0;           // momentum override (per state entry) or nullptr
+    uint64_t seed;
+    uint64_t sweep;
+    double* partials;           // kPart per tile
+    double* chain_edge;         // kEdge per chain
+    int32_t terms;
+};
+
+struct FinalizeArgs {
+    const ChainDesc* chains;
+    int32_t n_chains;
+    const double* partials;
+    const double* chain_edge;
+    rsv_theta* theta;
+    rsv_prior prior;
+    uint64_t seed;
+    uint64_t sweep;
+    int32_t terms;
+    int32_t do_metropolis;      // use dH + Metropolis; else stats of the current h
+    int32_t do_theta;
+    const double* log_u;        // override or nullptr
+    int32_t* accept_ws;         // per chain flag for the commit kernel
+    double* delta_h_out;        // per chain or nullptr
+    int32_t* accepted_out;      // per chain or nullptr
+    rsv_theta* theta_trace;     // per chain or nullptr
+    double* stats_out;          // 7 per chain or nullptr
+    uint32_t* counters;
+};
+
+// Launchers (rsv_kernels.hip).  Each returns the hipError_t of its launch.
+hipError_t launch_prepare(hipStream_t st, const double* y, const double* lrv, int64_t n,
+                          double* y2_d, float* y2_f, float* lrv_f);
+hipError_t launch_validate(hipStream_t st, const double* y, const double* lrv, int64_t n_data,
+                           const void* h, int64_t n_state, int precision, uint32_t* counters);
+hipError_t launch_traj(hipStream_t st, int precision, int S, bool mass, bool edge,
+                       const void* args);
+int traj_sites_per_lane(int precision, int requested);  // -1 if not compiled
+hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a);
+hipError_t launch_commit(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
+                         const int32_t* accept_ws, const void* h_prop, void* h_cur,
+                         void* h_trace, int precision);
+hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
+                        const ChainDesc* chains, const rsv_theta* theta, const void* h_cur,
+                        const double* lrv_d, double* partials, double* chain_edge, int precision);
+hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
+                          int32_t max_T, const float* log_mass, uint64_t seed, uint64_t sweep,
+                          double* p_out);
+hipError_t launch_count_nonfinite(hipStream_t st, const void* h, int64_t n, int precision,
+                                  uint32_t* counter);
+
+}  // namespace rsv

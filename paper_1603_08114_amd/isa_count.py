@@ -1,0 +1,91 @@
+"""Instruction counts of the leapfrog loop, read from the gfx950 assembly.
+
+Compiles csrc/rsv_kernels.hip to device assembly, finds in each trajectory
+kernel (identity mass, body tiles, RSV terms) the loop that carries the DPP
+lane shifts -- one leapfrog step over a lane's S sites -- and counts its VALU
+instructions.  Dividing by S gives VALU instructions per site-update, the
+per-unit figure of the ALU roofline.  Writes isa_counts.json next to this file.
+"""
+import json
+import os
+import re
+import subprocess
+import sys
+import tempfile
+from collections import Counter
+
+from . import build as B
+
+OUT = os.path.join(B.PKG, "isa_counts.json")
+VARIANTS = {("f64", 8): "IdLi8ELb0ELb0ELb1E", ("f64", 16): "IdLi16ELb0ELb0ELb1E",
+            ("f32", 16): "IfLi16ELb0ELb0ELb1E", ("f32", 32): "IfLi32ELb0ELb0ELb1E"}
+
+
+def assemble() -> str:
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "k.s")
+        cmd = ["hipcc", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, "--cuda-device-only", "-S",
+               os.path.join(B.CSRC, "rsv_kernels.hip"), "-o", out]
+        subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
+        return open(out).read()
+
+
+def kernel_text(asm: str, tag: str) -> str:
+    m = re.search(r"^(_ZN3rsv\w*k_traj" + tag + r"\w*):", asm, re.M)
+    if not m:
+        raise KeyError(tag)
+    body = asm[m.end():]
+    return body[: body.index("s_endpgm")], m.group(1)
+
+
+def descriptor(asm: str, name: str) -> dict:
+    m = re.search(r"\.amdhsa_kernel " + re.escape(name) + r"(.*?)\.end_amdhsa_kernel", asm, re.S)
+    get = lambda k: int(re.search(r"\." + k + r" (\d+)", m.group(1)).group(1))
+    return {"vgpr": get("amdhsa_next_free_vgpr"), "sgpr": get("amdhsa_next_free_sgpr"),
+            "scratch_bytes": get("amdhsa_private_segment_fixed_size")}
+
+
+def leapfrog_loop(text: str):
+    lines = [l.strip() for l in text.split("\n")]
+    labels = {}
+    for i, l in enumerate(lines):
+        m = re.match(r"^(\.LBB\w+):", l)
+        if m:
+            labels[m.group(1)] = i
+    best = None
+    for i, l in enumerate(lines):
+        m = re.match(r"s_cbranch_\w+ (\.LBB\w+)|s_branch (\.LBB\w+)", l)
+        tgt = m and (m.group(1) or m.group(2))
+        if tgt in labels and labels[tgt] < i:
+            seg = [x for x in lines[labels[tgt]:i + 1]
+                   if x and not x.startswith((";", ".")) and not x.endswith(":")]
+            if any("_dpp" in x for x in seg) and (best is None or len(seg) > len(best)):
+                best = seg
+    return Counter(x.split()[0] for x in best)
+
+
+def count(asm: str) -> dict:
+    table = {}
+    for (prec, S), tag in VARIANTS.items():
+        text, name = kernel_text(asm, tag)
+        ops = leapfrog_loop(text)
+        valu = sum(v for k, v in ops.items() if k.startswith("v_"))
+        fp = sum(v for k, v in ops.items() if k.startswith("v_") and prec in k)
+        table[f"{prec}_S{S}"] = dict(
+            loop_instructions=sum(ops.values()), valu_per_site_update=valu / S,
+            fp_valu_per_site_update=fp / S, **descriptor(asm, name),
+            top_ops=dict(ops.most_common(12)))
+    return table
+
+
+def main():
+    table = count(assemble())
+    with open(OUT, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    print(json.dumps({k: round(v["valu_per_site_update"], 3) for k, v in table.items()}))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

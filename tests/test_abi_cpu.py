@@ -1,0 +1,87 @@
+"""The C-ABI library loads without a GPU, exports every symbol its header
+declares, and rejects invalid problems on the host before any device call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1603_08114_amd import _lib, api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsv_hmc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsv_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rsv_hmc_init", "rsv_hmc_trajectory", "rsv_hmc_sweep", "rsv_theta_update"):
+        assert required in names
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(_lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header_layout():
+    assert C.sizeof(_lib.rsv_theta) == 40
+    assert C.sizeof(_lib.rsv_prior) == 64
+    assert C.sizeof(_lib.rsv_leapfrog) == 16
+    assert C.sizeof(_lib.rsv_problem) == 4 + 4 + 8 * 3 + 4 * 4 + 8 + 64
+    assert C.sizeof(_lib.rsv_trace) == 32
+
+
+def _pb(offsets, **kw):
+    return api.Problem(offsets=np.asarray(offsets), y=None, log_rv=None, **kw)
+
+
+def test_workspace_and_state_sizes():
+    pb = _pb([0, 1000, 5000], chains_per_series=4, max_steps=30)
+    assert api.rsv_hmc_state_size(pb) == 4 * 5000
+    n64 = api.rsv_hmc_workspace_bytes(pb)
+    pb32 = _pb([0, 1000, 5000], chains_per_series=4, max_steps=30, precision=_lib.RSV_F32_MIXED)
+    assert n64 > 0 and api.rsv_hmc_workspace_bytes(pb32) > 0
+    # the proposal buffer alone is n_state * 8 bytes in FP64
+    assert n64 >= 4 * 5000 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(offsets=[0, 2]),                         # T < 3
+    dict(offsets=[1, 5]),                         # offsets[0] != 0
+    dict(offsets=[0, 100], max_steps=0),
+    dict(offsets=[0, 100], precision=7),
+    dict(offsets=[0, 100], terms=0),
+    dict(offsets=[0, 100], sites_per_lane=5),
+    dict(offsets=[0, 100], chains_per_series=0),
+    dict(offsets=[0, 5000], max_steps=400, sites_per_lane=8),   # halo wider than a tile
+    dict(offsets=[0, 100], prior=dict(mu_var=-1.0)),
+])
+def test_invalid_problems_rejected_on_host(bad):
+    offsets = bad.pop("offsets")
+    pb = _pb(offsets, **bad)
+    with pytest.raises(api.RSVError) as e:
+        api.rsv_hmc_workspace_bytes(pb)
+    assert e.value.status == _lib.RSV_EINVAL
+    assert len(_lib.load().rsv_last_error()) > 0
+    # init fails the same way, before touching a device
+    ctx = C.c_void_p()
+    st = _lib.load().rsv_hmc_init(C.byref(ctx), C.byref(pb.struct()), None, None, None, None,
+                                  0, None)
+    assert st == _lib.RSV_EINVAL and not ctx.value
+
+
+def test_null_context_is_a_state_error():
+    lib = _lib.load()
+    lf = (_lib.rsv_leapfrog * 1)()
+    assert lib.rsv_hmc_trajectory(None, 0, lf, None, None, None, None) == _lib.RSV_ESTATE
+    assert lib.rsv_theta_update(None, 0, None) == _lib.RSV_ESTATE
+    assert lib.rsv_hmc_sweep(None, 0, 1, lf, 1, None) == _lib.RSV_ESTATE
