@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--dtau", type=float, default=0.0, help="0 = tune to ~80%% acceptance")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--sites-per-lane", type=int, default=0)
+    ap.add_argument("--sites-per-lane", type=int, default=8)
+    ap.add_argument("--waves-per-tile", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
@@ -72,13 +73,13 @@ def tune_dtau(smp, k, T, first_sweep, target=0.8):
     return dtau, acc, sweep
 
 
-def isa_figures(precision, S):
+def isa_figures(precision, S, NW):
     path = os.path.join(ROOT, "paper_1603_08114_amd", "isa_counts.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         table = json.load(f)
-    return table.get(f"{precision}_S{S}")
+    return table.get(f"{precision}_S{S}_W{NW}")
 
 
 def cpu_baseline(y, lr, h0, theta, k, dtau, n_sweeps, seed, T):
@@ -112,9 +113,11 @@ def main():
     y, lr, h_true = synth.simulate_rsv_long(T, theta, args.seed)
     prec = RSV_F64 if args.precision == "f64" else RSV_F32_MIXED
     smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
-                         precision=prec, sites_per_lane=args.sites_per_lane)
-    S = int(smp.pb.sites_per_lane) or (8 if prec == RSV_F64 else 16)
-    print(f"[bench] T={T} k={k} precision={args.precision} S={S}", file=sys.stderr, flush=True)
+                         precision=prec, sites_per_lane=args.sites_per_lane,
+                         waves_per_tile=args.waves_per_tile)
+    S, NW = args.sites_per_lane, args.waves_per_tile
+    print(f"[bench] T={T} k={k} precision={args.precision} S={S} NW={NW}", file=sys.stderr,
+          flush=True)
 
     sweep = 0
     if args.dtau > 0:
@@ -150,7 +153,7 @@ def main():
     value = site_updates / elapsed
     kern_avg = kern_ms / 1e3 / max(n_rec, 1)
     traj_rate = float(T) * k / kern_avg
-    isa = isa_figures(args.precision, S)
+    isa = isa_figures(args.precision, S, NW)
     peak = FP64_PEAK_TFLOPS if args.precision == "f64" else FP32_PEAK_TFLOPS
     roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
             "traffic": None, "kernel": "k_traj", "avg_launch_ms": kern_avg * 1e3,
@@ -179,7 +182,8 @@ def main():
         "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
         "config": {"workload": f"single-series RSV HMC sweep, T={T}, k={k}, "
                                f"{args.precision.upper()}, theta updated every sweep",
-                   "T": T, "k": k, "dtau": dtau, "chains": 1, "sites_per_lane": S},
+                   "T": T, "k": k, "dtau": dtau, "chains": 1, "sites_per_lane": S,
+                   "waves_per_tile": NW},
         "roofline": roof,
         "acceptance": acc_rate,
         "traj_kernel_site_updates_per_s": traj_rate,

@@ -92,10 +92,12 @@ typedef struct {
     int32_t max_steps;          /* largest k any later call will use (>= 1)    */
     int32_t sites_per_lane;     /* tile shape of the trajectory kernel: sites
                                    held by each lane (0 = library default;
-                                   RSV_F64: 8 or 16, RSV_F32_MIXED: 16 or 32);
-                                   a wavefront integrates 64 * sites_per_lane
-                                   sites, of which all but a k+1 halo on each
-                                   cut side are exact                          */
+                                   RSV_F64: 4 or 8, RSV_F32_MIXED: 8 or 16)    */
+    int32_t waves_per_tile;     /* wavefronts per tile (0 = default; 1 or 4).
+                                   A tile spans 64 * waves_per_tile *
+                                   sites_per_lane sites, of which all but a
+                                   k+1 halo on each cut side are exact          */
+    int32_t reserved;
     uint64_t seed;              /* key of all random streams                   */
     rsv_prior prior;
 } rsv_problem;

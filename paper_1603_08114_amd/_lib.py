@@ -48,6 +48,8 @@ class rsv_problem(C.Structure):
         ("terms", C.c_int32),
         ("max_steps", C.c_int32),
         ("sites_per_lane", C.c_int32),
+        ("waves_per_tile", C.c_int32),
+        ("reserved", C.c_int32),
         ("seed", C.c_uint64),
         ("prior", rsv_prior),
     ]

@@ -66,6 +66,7 @@ class Problem:
     terms: int = L.RSV_TERMS_RSV
     max_steps: int = 50
     sites_per_lane: int = 0
+    waves_per_tile: int = 0
     seed: int = 0
     prior: dict = field(default_factory=lambda: dict(DEFAULT_PRIOR))
 
@@ -91,6 +92,7 @@ class Problem:
         pb.terms = int(self.terms)
         pb.max_steps = int(self.max_steps)
         pb.sites_per_lane = int(self.sites_per_lane)
+        pb.waves_per_tile = int(self.waves_per_tile)
         pb.seed = int(self.seed)
         pr = dict(DEFAULT_PRIOR)
         pr.update(self.prior or {})
@@ -196,7 +198,8 @@ class RSVSampler:
 
     def __init__(self, offsets, y, log_rv, h0, theta0, chains_per_series=1,
                  precision=L.RSV_F64, terms=L.RSV_TERMS_RSV, max_steps=50, seed=0,
-                 prior=None, log_mass=None, sites_per_lane=0, device="cuda"):
+                 prior=None, log_mass=None, sites_per_lane=0, waves_per_tile=0,
+                 device="cuda"):
         if not torch.cuda.is_available():
             raise RuntimeError("RSVSampler needs a GPU (HIP device)")
         self.device = torch.device(device)
@@ -205,7 +208,8 @@ class RSVSampler:
         self.log_rv = torch.as_tensor(np.asarray(log_rv, np.float64), **to).contiguous()
         self.pb = Problem(offsets=np.asarray(offsets, np.int64), y=self.y, log_rv=self.log_rv,
                           chains_per_series=chains_per_series, precision=precision, terms=terms,
-                          max_steps=max_steps, sites_per_lane=sites_per_lane, seed=seed,
+                          max_steps=max_steps, sites_per_lane=sites_per_lane,
+                          waves_per_tile=waves_per_tile, seed=seed,
                           prior=prior or dict(DEFAULT_PRIOR))
         state_dtype = torch.float64 if precision == L.RSV_F64 else torch.float32
         self.n_state = rsv_hmc_state_size(self.pb)

@@ -43,37 +43,38 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int halo_for(int n_steps) { return (n_steps + 1 + 3) & ~3; }
 
-// Tile decomposition of one chain of length T for S sites per lane and a
-// trajectory of n_steps: tiles of 64*S loaded sites whose exact ranges
-// [a, b) partition [0, T).  Returns false if the halo does not fit.
-bool tile_chain(int32_t chain, int32_t T, int S, int n_steps, std::vector<TileDesc>& body,
-                std::vector<TileDesc>& edges) {
-    const int L = 64 * S;
+// Tile decomposition of one chain of length T for tiles of NW wavefronts
+// with S sites per lane and a trajectory of n_steps: tiles of 64*NW*S loaded
+// sites whose exact ranges [a, b) partition [0, T).  Returns false if the
+// halo does not fit.
+bool tile_chain(int32_t chain, int32_t T, int S, int NW, int n_steps,
+                std::vector<TileDesc>& body, std::vector<TileDesc>& edges) {
+    const int L = 64 * NW * S;
     const int H = halo_for(n_steps);
     if (T <= L) {
-        const TileDesc t{chain, 0, 0, T};
-        if (T % S != 0) edges.push_back(t); else body.push_back(t);
+        const TileDesc t{chain, 0, 0, T, T % S != 0 ? 1 : 0, {0, 0, 0}};
+        if (t.edge) edges.push_back(t); else body.push_back(t);
         return true;
     }
     if (L <= 2 * H) return false;
     int32_t a = 0, b = L - H;
-    body.push_back(TileDesc{chain, 0, a, b});
+    body.push_back(TileDesc{chain, 0, a, b, 0, {0, 0, 0}});
     for (;;) {
         a = b;
         const int32_t la = a - H;
         if (la + L >= T) {
-            const TileDesc t{chain, la, a, T};
-            if ((T - la) % S != 0) edges.push_back(t); else body.push_back(t);
+            const TileDesc t{chain, la, a, T, (T - la) % S != 0 ? 1 : 0, {0, 0, 0}};
+            if (t.edge) edges.push_back(t); else body.push_back(t);
             return true;
         }
         b = la + L - H;
-        body.push_back(TileDesc{chain, la, a, b});
+        body.push_back(TileDesc{chain, la, a, b, 0, {0, 0, 0}});
     }
 }
 
-int32_t count_tiles(int32_t T, int S, int n_steps) {
+int32_t count_tiles(int32_t T, int S, int NW, int n_steps) {
     std::vector<TileDesc> b, e;
-    if (!tile_chain(0, T, S, n_steps, b, e)) return -1;
+    if (!tile_chain(0, T, S, NW, n_steps, b, e)) return -1;
     return static_cast<int32_t>(b.size() + e.size());
 }
 
@@ -111,20 +112,30 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     return RSV_OK;
 }
 
+rsv_status tile_shape(const rsv_problem* pb, int* S, int* NW) {
+    traj_default_shape(pb->precision, S, NW);
+    if (pb->sites_per_lane) *S = pb->sites_per_lane;
+    if (pb->waves_per_tile) *NW = pb->waves_per_tile;
+    if (!traj_shape_available(pb->precision, *S, *NW))
+        return fail(RSV_EINVAL, "tile shape (sites_per_lane %d, waves_per_tile %d) is not "
+                                "compiled for this precision", *S, *NW);
+    return RSV_OK;
+}
+
 rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     int64_t n_data = 0, n_state = 0;
     rsv_status st = check_problem(pb, &n_data, &n_state);
     if (st != RSV_OK) return st;
-    const int S = traj_sites_per_lane(pb->precision, pb->sites_per_lane);
-    if (S < 0) return fail(RSV_EINVAL, "sites_per_lane = %d is not available for this precision",
-                           pb->sites_per_lane);
+    int S = 0, NW = 0;
+    rsv_status sh = tile_shape(pb, &S, &NW);
+    if (sh != RSV_OK) return sh;
     int64_t tiles = 0;
     for (int s = 0; s < pb->n_series; ++s) {
         const int32_t T = static_cast<int32_t>(pb->offsets[s + 1] - pb->offsets[s]);
-        const int32_t n = count_tiles(T, S, pb->max_steps);
+        const int32_t n = count_tiles(T, S, NW, pb->max_steps);
         if (n < 0)
             return fail(RSV_EINVAL, "max_steps = %d needs a halo wider than a tile (%d sites)",
-                        pb->max_steps, 64 * S);
+                        pb->max_steps, 64 * NW * S);
         tiles += static_cast<int64_t>(n) * pb->chains_per_series;
     }
     if (tiles > (int64_t(1) << 30)) return fail(RSV_EINVAL, "too many tiles");
@@ -158,7 +169,7 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
 struct rsv_ctx {
     rsv_problem pb;
     std::vector<int64_t> offsets;
-    int32_t n_chains = 0, C = 0, S = 0, max_T = 0;
+    int32_t n_chains = 0, C = 0, S = 0, NW = 0, max_T = 0;
     int64_t n_data = 0, n_state = 0;
     void* h = nullptr;
     rsv_theta* theta = nullptr;
@@ -175,13 +186,14 @@ struct rsv_ctx {
     ChainDesc* chains = nullptr;
     double* partials = nullptr;
     double* edge = nullptr;
-    int32_t* accept = nullptr;
+    int32_t* accept = nullptr;  // per chain: 1 if its current state is in h_prop
     uint32_t* counters = nullptr;
     // host mirrors of the current decomposition
     std::vector<rsv_leapfrog> lf;
     std::vector<TileDesc> h_tiles;
     std::vector<ChainDesc> h_chains;
     int32_t n_body = 0, n_edge = 0;
+    int32_t max_tiles_per_chain = 0;
     // kernel timing: event pairs around each trajectory-kernel launch
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
@@ -216,7 +228,7 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
             d.series = s;
             d.tile_begin = static_cast<int32_t>(body.size());
             const size_t n_edge_before = edges.size();
-            if (!tile_chain(ch, T, c->S, lf[s].n_steps, body, edges))
+            if (!tile_chain(ch, T, c->S, c->NW, lf[s].n_steps, body, edges))
                 return fail(RSV_EINVAL, "series %d: n_steps %d too large for a tile", s,
                             lf[s].n_steps);
             d.tile_count = static_cast<int32_t>(body.size()) - d.tile_begin;
@@ -227,12 +239,19 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
     }
     const int32_t n_total = static_cast<int32_t>(body.size() + edges.size());
     if (n_total > c->lay.max_tiles) return fail(RSV_ENOMEM, "tile count exceeds the workspace");
-    for (int32_t ch = 0; ch < c->n_chains; ++ch)
-        chains[ch].edge_tile = edge_of[ch] < 0 ? -1 : static_cast<int32_t>(body.size()) + edge_of[ch];
+    // edge tiles (slower per site) go first so that they start in the first round
+    const int32_t n_edge = static_cast<int32_t>(edges.size());
+    for (int32_t ch = 0; ch < c->n_chains; ++ch) {
+        chains[ch].edge_tile = edge_of[ch];
+        chains[ch].tile_begin += n_edge;
+    }
+    c->max_tiles_per_chain = 0;
+    for (const ChainDesc& d : chains)
+        c->max_tiles_per_chain = std::max(c->max_tiles_per_chain, d.tile_count + 1);
     c->n_body = static_cast<int32_t>(body.size());
     c->n_edge = static_cast<int32_t>(edges.size());
-    c->h_tiles = body;
-    c->h_tiles.insert(c->h_tiles.end(), edges.begin(), edges.end());
+    c->h_tiles = edges;
+    c->h_tiles.insert(c->h_tiles.end(), body.begin(), body.end());
     c->h_chains = chains;
     RSV_HIP(hipMemcpyAsync(c->tiles, c->h_tiles.data(), c->h_tiles.size() * sizeof(TileDesc),
                            hipMemcpyHostToDevice, c->stream));
@@ -259,8 +278,9 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.n_list = 0;
     a.chains = c->chains;
     a.theta = c->theta;
-    a.h_cur = static_cast<const R*>(c->h);
-    a.h_prop = static_cast<R*>(c->h_prop);
+    a.h_a = static_cast<const R*>(c->h);
+    a.h_b = static_cast<R*>(c->h_prop);
+    a.state_sel = c->accept;
     if constexpr (sizeof(R) == sizeof(double)) {
         a.y2 = reinterpret_cast<const R*>(c->y2_d);
         a.lrv = reinterpret_cast<const R*>(c->pb.log_rv);
@@ -287,11 +307,8 @@ rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0) {
     const bool timed = c->ev_used < c->ev_start.size();
     if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
     a.tile_first = 0;
-    a.n_list = c->n_body;
-    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, mass, false, &a));
-    a.tile_first = c->n_body;
-    a.n_list = c->n_edge;
-    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, mass, true, &a));
+    a.n_list = c->n_body + c->n_edge;
+    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, c->NW, mass, &a));
     if (timed) RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used++], c->stream));
     return RSV_OK;
 }
@@ -315,15 +332,23 @@ rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const do
     f.do_metropolis = 1;
     f.do_theta = do_theta;
     f.log_u = log_u;
-    f.accept_ws = c->accept;
+    f.state_sel = c->accept;
     f.delta_h_out = delta_h;
     f.accepted_out = accepted;
     f.theta_trace = theta_trace;
     f.stats_out = stats_out;
     f.counters = c->counters;
-    RSV_HIP(launch_finalize(c->stream, f));
-    RSV_HIP(launch_commit(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h_prop, c->h,
-                          h_trace, c->pb.precision));
+    RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
+    if (h_trace)
+        RSV_HIP(launch_gather_state(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
+                                    c->h_prop, h_trace, c->pb.precision));
+    return RSV_OK;
+}
+
+// Leave every chain's current state in the caller's buffer.
+rsv_status settle(rsv_ctx* c) {
+    RSV_HIP(launch_settle(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h, c->h_prop,
+                          c->pb.precision));
     return RSV_OK;
 }
 
@@ -366,7 +391,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->pb.offsets = c->offsets.data();
     c->C = pb->chains_per_series;
     c->n_chains = pb->n_series * pb->chains_per_series;
-    c->S = traj_sites_per_lane(pb->precision, pb->sites_per_lane);
+    tile_shape(pb, &c->S, &c->NW);
     c->n_data = c->offsets[pb->n_series];
     c->n_state = c->n_data * c->C;
     for (int s = 0; s < pb->n_series; ++s)
@@ -403,6 +428,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
 
     RSV_HIP_INIT(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(uint32_t), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->edge, 0, c->n_chains * kEdge * sizeof(double), c->stream));
+    RSV_HIP_INIT(hipMemsetAsync(c->accept, 0, c->n_chains * sizeof(int32_t), c->stream));
     RSV_HIP_INIT(launch_prepare(c->stream, pb->y, pb->log_rv, c->n_data, c->y2_d, c->y2_f,
                                 c->lrv_f));
     RSV_HIP_INIT(launch_validate(c->stream, pb->y, pb->log_rv, c->n_data, h, c->n_state,
@@ -448,13 +474,15 @@ rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf
     if (!c) return fail(RSV_ESTATE, "context is NULL");
     rsv_status st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
-    return run_trajectory(c, sweep, p0, log_u, delta_h, accepted, 0, nullptr, nullptr, nullptr);
+    st = run_trajectory(c, sweep, p0, log_u, delta_h, accepted, 0, nullptr, nullptr, nullptr);
+    return st != RSV_OK ? st : settle(c);
 }
 
 rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
     RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
-                         c->pb.log_rv, c->partials, c->edge, c->pb.precision));
+                         c->h_prop, c->accept, c->pb.log_rv, c->partials, c->edge,
+                         c->pb.precision));
     FinalizeArgs f;
     f.chains = c->chains;
     f.n_chains = c->n_chains;
@@ -468,13 +496,13 @@ rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
     f.do_metropolis = 0;
     f.do_theta = 1;
     f.log_u = nullptr;
-    f.accept_ws = c->accept;
+    f.state_sel = c->accept;
     f.delta_h_out = nullptr;
     f.accepted_out = nullptr;
     f.theta_trace = nullptr;
     f.stats_out = suff_stats;
     f.counters = c->counters;
-    RSV_HIP(launch_finalize(c->stream, f));
+    RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
     return RSV_OK;
 }
 
@@ -497,7 +525,7 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
                             update_theta ? 1 : 0, tt, ht, nullptr);
         if (st != RSV_OK) return st;
     }
-    return RSV_OK;
+    return settle(c);
 }
 
 rsv_status rsv_hmc_check(rsv_ctx* c, int64_t* n_nonfinite) {

@@ -8,8 +8,9 @@
 
 namespace rsv {
 
-// A tile is the part of one chain that one wavefront integrates through a
-// whole trajectory.  It loads sites [la, la + 64*S) (clipped to [0, T)),
+// A tile is the part of one chain that one group of NW wavefronts integrates
+// through a whole trajectory.  It loads sites [la, la + 64*NW*S) (clipped to
+// [0, T)),
 // and after k steps the sites [a, b) are exact; the halo on either side is
 // at least k+1 sites (absent at the ends of the series).  la is a multiple
 // of 4 so that each lane's sites are whole Philox blocks.
@@ -18,6 +19,8 @@ struct TileDesc {
     int32_t la;
     int32_t a;
     int32_t b;
+    int32_t edge;  // 1 if the chain's last site lies strictly inside a lane
+    int32_t pad[3];
 };
 
 struct ChainDesc {
@@ -50,8 +53,9 @@ struct TrajArgs {
     int32_t n_list;
     const ChainDesc* chains;
     const rsv_theta* theta;
-    const R* h_cur;
-    R* h_prop;
+    const R* h_a;               // the caller's state buffer
+    R* h_b;                     // the workspace's second state buffer
+    const int32_t* state_sel;   // per chain: 1 if its current state is in h_b
     const R* y2;                // y_t^2 in R
     const R* lrv;               // ln RV_t in R
     const double* y2_d;         // FP64 copies for dH and the statistics
@@ -78,7 +82,7 @@ struct FinalizeArgs {
     int32_t do_metropolis;      // use dH + Metropolis; else stats of the current h
     int32_t do_theta;
     const double* log_u;        // override or nullptr
-    int32_t* accept_ws;         // per chain flag for the commit kernel
+    int32_t* state_sel;         // per chain: flipped when the proposal is accepted
     double* delta_h_out;        // per chain or nullptr
     int32_t* accepted_out;      // per chain or nullptr
     rsv_theta* theta_trace;     // per chain or nullptr
@@ -91,16 +95,22 @@ hipError_t launch_prepare(hipStream_t st, const double* y, const double* lrv, in
                           double* y2_d, float* y2_f, float* lrv_f);
 hipError_t launch_validate(hipStream_t st, const double* y, const double* lrv, int64_t n_data,
                            const void* h, int64_t n_state, int precision, uint32_t* counters);
-hipError_t launch_traj(hipStream_t st, int precision, int S, bool mass, bool edge,
+hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
                        const void* args);
-int traj_sites_per_lane(int precision, int requested);  // -1 if not compiled
-hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a);
-hipError_t launch_commit(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
-                         const int32_t* accept_ws, const void* h_prop, void* h_cur,
-                         void* h_trace, int precision);
+bool traj_shape_available(int precision, int S, int NW);
+void traj_default_shape(int precision, int* S, int* NW);
+hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain);
+// Copy every chain's current state (selected by state_sel) into h_dst.
+hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
+                               int32_t max_T, const int32_t* state_sel, const void* h_a,
+                               const void* h_b, void* h_dst, int precision);
+// Move chains whose current state is in h_b back into h_a and clear state_sel.
+hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
+                         int32_t* state_sel, void* h_a, const void* h_b, int precision);
 hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
-                        const ChainDesc* chains, const rsv_theta* theta, const void* h_cur,
-                        const double* lrv_d, double* partials, double* chain_edge, int precision);
+                        const ChainDesc* chains, const rsv_theta* theta, const void* h_a,
+                        const void* h_b, const int32_t* state_sel, const double* lrv_d,
+                        double* partials, double* chain_edge, int precision);
 hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                           int32_t max_T, const float* log_mass, uint64_t seed, uint64_t sweep,
                           double* p_out);

@@ -9,6 +9,7 @@
 // without touching HBM.  Sites within k+1 of a tile's cut are recomputed by
 // the neighbouring tile (halo), so every exact site is produced once.
 #include "rsv_device.h"
+#include "rsv_exp.h"
 #include "rsv_internal.h"
 
 namespace rsv {
@@ -25,27 +26,35 @@ __device__ inline R ghost_neighbour(R h, R mu, R phi) {
 template <typename R>
 __device__ inline R exp_neg(R x);
 template <>
-__device__ inline double exp_neg<double>(double x) { return exp(-x); }
+__device__ inline double exp_neg<double>(double x) { return exp_fast(-x); }
 template <>
-__device__ inline float exp_neg<float>(float x) { return expf(-x); }
+__device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
 
 // ---------------------------------------------------------------------------
 // Trajectory kernel: momentum refresh, k leapfrog steps, per-site dH terms and
-// sufficient statistics of h' and h, all for one tile per wavefront.
+// sufficient statistics of h' and h, for one tile per group of NW wavefronts.
+// Lane g = 64*wave + lane of a tile holds sites [la + g*S, la + (g+1)*S).
+// Within a wavefront the end sites of each lane move by DPP lane shifts;
+// between the NW wavefronts of a tile they pass through LDS (one barrier per
+// leapfrog step, slots double-buffered by step parity).
 // ---------------------------------------------------------------------------
-template <typename R, int S, bool MASS, bool EDGE, bool RET>
-__global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
-    static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (w >= A.n_list) return;  // uniform over the wavefront
-    const int tile_id = A.tile_first + w;
+template <typename R, int NW>
+struct TileShared {
+    R left[2][NW];   // h of the first site of each wavefront
+    R right[2][NW];  // h of the last site of each wavefront
+    double red[NW][11];
+    double up1[NW], up0[NW];
+};
+
+template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET>
+__device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW>& sh,
+                                          const int tile_id, const int wv, const int lane) {
     const TileDesc td = A.tiles[tile_id];
     const ChainDesc cd = A.chains[td.chain];
     const rsv_theta th = A.theta[td.chain];
 
     const int T = cd.T;
-    const int t0 = td.la + lane * S;
+    const int t0 = td.la + (wv * kWave + lane) * S;
     const bool rv = (A.terms & RSV_TERM_RV) != 0;
     const double phi = th.phi, mu = th.mu, xi = th.xi;
     const double inv_se = 1.0 / th.sig2_eta;
@@ -62,7 +71,9 @@ __global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
     R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1];
     double kin0 = 0.0;  // kinetic energy of the exact sites at the start
 
-    const R* hc = A.h_cur + cd.h_off;
+    const bool in_b = A.state_sel[td.chain] != 0;
+    const R* hc = (in_b ? A.h_b : A.h_a) + cd.h_off;
+    R* hp = (in_b ? const_cast<R*>(A.h_a) : A.h_b) + cd.h_off;
     const R* y2 = A.y2 + cd.d_off;
     const R* lr = A.lrv + cd.d_off;
 #pragma unroll
@@ -134,6 +145,14 @@ __global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
     for (int step = 0; step < cd.n_steps; ++step) {
         R hl0 = from_lower(h[S - 1]);
         R hrS = from_upper(h[0]);
+        if constexpr (NW > 1) {
+            const int par = step & 1;
+            if (lane == 0) sh.left[par][wv] = h[0];
+            if (lane == kWave - 1) sh.right[par][wv] = h[S - 1];
+            __syncthreads();
+            if (lane == 0 && wv > 0) hl0 = sh.right[par][wv - 1];
+            if (lane == kWave - 1 && wv < NW - 1) hrS = sh.left[par][wv + 1];
+        }
         if (lane_first) hl0 = ghost_neighbour(h[0], mu_r, phi_r);
         if (lane_last) hrS = ghost_neighbour(h[S - 1], mu_r, phi_r);
 #pragma unroll
@@ -168,13 +187,23 @@ __global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
         const int t = t0 + j;
         h0d[j] = (t < T) ? static_cast<double>(hc[t]) : 0.0;
     }
-    const double h1_up = static_cast<double>(from_upper(h[0]));
-    const double h0_up = from_upper(h0d[0]);
+    double h1_up = static_cast<double>(from_upper(h[0]));
+    double h0_up = from_upper(h0d[0]);
+    if constexpr (NW > 1) {
+        if (lane == 0) {
+            sh.up1[wv] = static_cast<double>(h[0]);
+            sh.up0[wv] = h0d[0];
+        }
+        __syncthreads();
+        if (lane == kWave - 1 && wv < NW - 1) {
+            h1_up = sh.up1[wv + 1];
+            h0_up = sh.up0[wv + 1];
+        }
+    }
 
     double dH = -kin0;
     double s1[5] = {0, 0, 0, 0, 0}, s0[5] = {0, 0, 0, 0, 0};
     double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
-    R* hp = A.h_prop + cd.h_off;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
@@ -217,21 +246,51 @@ __global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
         hp[t] = h[j];
     }
 
-    dH = wave_sum(dH);
+    double red[11];
+    red[kPartDH] = wave_sum(dH);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        s1[q] = wave_sum(s1[q]);
-        s0[q] = wave_sum(s0[q]);
+        red[kPartProp + q] = wave_sum(s1[q]);
+        red[kPartCur + q] = wave_sum(s0[q]);
+    }
+    if constexpr (NW > 1) {
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 11; ++q) sh.red[wv][q] = red[q];
+        }
+        __syncthreads();
+        if (wv != 0) return;
+#pragma unroll
+        for (int q = 0; q < 11; ++q) {
+            double v = sh.red[0][q];
+            for (int x = 1; x < NW; ++x) v += sh.red[x][q];
+            red[q] = v;
+        }
     }
     if (lane == 0) {
         double* out = A.partials + static_cast<int64_t>(tile_id) * kPart;
-        out[kPartDH] = dH;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            out[kPartProp + q] = s1[q];
-            out[kPartCur + q] = s0[q];
-        }
+        for (int q = 0; q < 11; ++q) out[q] = red[q];
     }
+}
+
+// One launch covers every tile; tiles whose chain ends inside a lane (EDGE)
+// take the variant that substitutes the end-point neighbour per site.
+template <typename R, int S, int NW, bool MASS, bool RET>
+__global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
+    static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
+    static_assert(NW == 1 || NW == 4, "one tile per wavefront or per 256-thread block");
+    constexpr int kTilesPerBlock = 4 / NW;
+    __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv_blk = threadIdx.x / kWave;
+    const int w = blockIdx.x * kTilesPerBlock + wv_blk / NW;
+    if (w >= A.n_list) return;  // uniform over the tile's wavefronts
+    const int tile_id = A.tile_first + w;
+    if (A.tiles[tile_id].edge)
+        traj_tile<R, S, NW, MASS, true, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
+    else
+        traj_tile<R, S, NW, MASS, false, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +299,8 @@ __global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
 template <typename R>
 __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_tiles,
                                                const ChainDesc* chains, const rsv_theta* theta,
-                                               const R* h, const double* lrv_d,
+                                               const R* h_a, const R* h_b,
+                                               const int32_t* state_sel, const double* lrv_d,
                                                double* partials, double* chain_edge) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -248,7 +308,7 @@ __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_
     const TileDesc td = tiles[w];
     const ChainDesc cd = chains[td.chain];
     const rsv_theta th = theta[td.chain];
-    const R* hc = h + cd.h_off;
+    const R* hc = (state_sel[td.chain] ? h_b : h_a) + cd.h_off;
     const double* lr = lrv_d + cd.d_off;
     double s[5] = {0, 0, 0, 0, 0};
     for (int t = td.a + lane; t < td.b; t += kWave) {
@@ -271,49 +331,73 @@ __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_
 }
 
 // ---------------------------------------------------------------------------
-// theta update (one lane per chain): Gibbs mu -> phi -> sigma_eta^2 -> xi ->
-// sigma_u^2 from the sufficient statistics; random numbers from the theta
-// stream: block 0 (z_mu, z_phi, u_phi), block 1 (z_xi), blocks 2.. and 34..
-// the Gamma attempts of sigma_eta^2 and sigma_u^2.
+// theta update: Gibbs mu -> phi -> sigma_eta^2 -> xi -> sigma_u^2 from the
+// sufficient statistics.  Random numbers come from the theta stream: block 0
+// (z_mu, z_phi, u_phi), block 1 (z_xi), blocks 2..33 and 34..65 the Gamma
+// attempts of sigma_eta^2 and sigma_u^2 (Marsaglia-Tsang, no squeeze; the
+// first accepted attempt is the draw).  None of these depends on the other
+// parameters except through the known Gamma shapes a + T/2, so one lane per
+// block evaluates them all in parallel; one lane then does the algebra.
 // ---------------------------------------------------------------------------
 constexpr int kGammaTries = 32;
-constexpr uint64_t kGammaEtaBlock = 2, kGammaUBlock = 2 + kGammaTries;
+constexpr int kGammaEtaBlock = 2, kGammaUBlock = 2 + kGammaTries;
+constexpr int kThetaBlocks = 2 + 2 * kGammaTries;
 
-struct ThetaStream {
-    uint64_t seed, sweep, chain;
-    __device__ void block(uint64_t idx, double u[4]) const {
-        uniforms4(seed, idx, sweep, chain, kTagTheta, u);
-    }
-    // Gamma(shape, 1), shape >= 1, by Marsaglia-Tsang squeeze-free acceptance.
-    __device__ double gamma(double shape, uint64_t first_block, bool& ran_out) const {
-#pragma clang fp contract(off)
-        const double d = shape - 1.0 / 3.0;
-        const double c = 1.0 / sqrt(9.0 * d);
-        for (int i = 0; i < kGammaTries; ++i) {
-            double u[4], x, unused;
-            block(first_block + static_cast<uint64_t>(i), u);
-            gauss_pair(u[0], u[1], x, unused);
-            double v = 1.0 + c * x;
-            if (v <= 0.0) continue;
-            v = v * v * v;
-            if (log(u[2]) < 0.5 * x * x + d - d * v + d * log(v)) return d * v;
-        }
-        ran_out = true;
-        return d;
-    }
+struct ThetaDraws {
+    double z_mu, z_phi, u_phi, z_xi, log_u_accept;
+    double g_val[kThetaBlocks];   // d v^3 of each Gamma attempt
+    int g_ok[kThetaBlocks];       // attempt accepted
 };
 
+// Block b of the theta stream (or, for b == kThetaBlocks, the Metropolis
+// uniform) for chain c.
+__device__ void theta_draw_block(int b, ThetaDraws& D, uint64_t seed, uint64_t sweep, uint64_t c,
+                                 double shape_eta, double shape_u) {
+#pragma clang fp contract(off)
+    double u[4];
+    if (b == kThetaBlocks) {
+        uniforms4(seed, 0, sweep, c, kTagAccept, u);
+        D.log_u_accept = log(u[0]);
+        return;
+    }
+    uniforms4(seed, static_cast<uint64_t>(b), sweep, c, kTagTheta, u);
+    double z0, z1;
+    gauss_pair(u[0], u[1], z0, z1);
+    if (b == 0) {
+        D.z_mu = z0;
+        D.z_phi = z1;
+        D.u_phi = u[2];
+    } else if (b == 1) {
+        D.z_xi = z0;
+    } else {
+        const double shape = b < kGammaUBlock ? shape_eta : shape_u;
+        const double d = shape - 1.0 / 3.0;
+        const double cc = 1.0 / sqrt(9.0 * d);
+        double v = 1.0 + cc * z0;
+        int ok = 0;
+        if (v > 0.0) {
+            v = v * v * v;
+            ok = log(u[2]) < 0.5 * z0 * z0 + d - d * v + d * log(v);
+        }
+        D.g_ok[b] = ok;
+        D.g_val[b] = ok ? d * v : d;
+    }
+}
+
+__device__ double first_gamma(const ThetaDraws& D, int first, bool& ran_out) {
+    for (int i = 0; i < kGammaTries; ++i)
+        if (D.g_ok[first + i]) return D.g_val[first + i];
+    ran_out = true;
+    return D.g_val[first];  // d, the attempt's fallback
+}
+
 __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
-                                 const rsv_prior& pr, int terms, const ThetaStream& rs,
+                                 const rsv_prior& pr, int terms, const ThetaDraws& D,
                                  bool& ran_out) {
 #pragma clang fp contract(off)
     const double B = st[0], B2 = st[1], BB = st[2], D1 = st[3], D2 = st[4];
     const double bf = st[5], bl = st[6];
     rsv_theta nxt = cur;
-
-    double u0[4], z_mu, z_phi;
-    rs.block(0, u0);
-    gauss_pair(u0[0], u0[1], z_mu, z_phi);
 
     // mu: Gaussian; precision from the stationary start and T-1 transitions
     {
@@ -324,7 +408,7 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
         const double lin = (pr.mu_mean - cur.mu) / pr.mu_var
                          + ((1.0 - cur.phi * cur.phi) * bf
                             + one_m_phi * ((B - bf) - cur.phi * (B - bl))) / cur.sig2_eta;
-        nxt.mu = cur.mu + lin / prec + z_mu / sqrt(prec);
+        nxt.mu = cur.mu + lin / prec + D.z_mu / sqrt(prec);
     }
     const double eps = nxt.mu - cur.mu;
     // a_t = b_t - eps;  Q(phi) = sum a^2 - 2 phi sum a_t a_{t+1} + phi^2 sum_{interior} a^2
@@ -333,28 +417,23 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
     const double inner = (B2 - bf * bf - bl * bl) - 2.0 * eps * (B - bf - bl) + (n - 2.0) * eps * eps;
     // phi: independence proposal from the Gaussian factor, corrected by sqrt(1-phi^2)
     {
-        const double cand = lag / inner + z_phi * sqrt(cur.sig2_eta / inner);
+        const double cand = lag / inner + D.z_phi * sqrt(cur.sig2_eta / inner);
         if (fabs(cand) < 1.0) {
             const double ratio = (1.0 - cand * cand) / (1.0 - cur.phi * cur.phi);
-            if (u0[2] * u0[2] < ratio) nxt.phi = cand;
+            if (D.u_phi * D.u_phi < ratio) nxt.phi = cand;
         }
     }
     {
         const double q = sum_aa - 2.0 * nxt.phi * lag + nxt.phi * nxt.phi * inner;
-        const double g = rs.gamma(pr.eta_shape + 0.5 * n, kGammaEtaBlock, ran_out);
-        nxt.sig2_eta = (pr.eta_scale + 0.5 * q) / g;
+        nxt.sig2_eta = (pr.eta_scale + 0.5 * q) / first_gamma(D, kGammaEtaBlock, ran_out);
     }
     if (terms & RSV_TERM_RV) {
-        double u1[4], z_xi, unused;
-        rs.block(1, u1);
-        gauss_pair(u1[0], u1[1], z_xi, unused);
         const double prec = 1.0 / pr.xi_var + n / cur.sig2_u;
         const double lin = (pr.xi_mean - cur.xi) / pr.xi_var + D1 / cur.sig2_u;
-        nxt.xi = cur.xi + lin / prec + z_xi / sqrt(prec);
+        nxt.xi = cur.xi + lin / prec + D.z_xi / sqrt(prec);
         const double f = nxt.xi - cur.xi;
         const double ss = D2 - 2.0 * f * D1 + n * f * f;
-        const double g = rs.gamma(pr.u_shape + 0.5 * n, kGammaUBlock, ran_out);
-        nxt.sig2_u = (pr.u_scale + 0.5 * ss) / g;
+        nxt.sig2_u = (pr.u_scale + 0.5 * ss) / first_gamma(D, kGammaUBlock, ran_out);
     }
     return nxt;
 }
@@ -363,50 +442,67 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
 // Per-chain finalize: reduce tile partials (compensated, fixed order), the
 // Metropolis test, the choice of statistics, and the theta update.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_finalize(FinalizeArgs A) {
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x;
-    const ChainDesc cd = A.chains[c];
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
+    constexpr int NW = NT / kWave;
     constexpr int NQ = 11;
+    __shared__ Comp part[NW][NQ];
+    __shared__ ThetaDraws draws;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const ChainDesc cd = A.chains[c];
+
+    // random numbers of this chain's Metropolis test and theta update
+    {
+        const double n = static_cast<double>(cd.T);
+        const int first = A.do_theta ? 0 : kThetaBlocks;
+        const int last = (A.do_metropolis && !A.log_u) ? kThetaBlocks : kThetaBlocks - 1;
+        for (int b = first + tid; b <= last; b += NT)
+            theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                             A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n);
+    }
+
     Comp acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
-    for (int i = lane; i < cd.tile_count; i += kWave) {
+    for (int i = tid; i < cd.tile_count; i += NT) {
         const double* pp = A.partials + static_cast<int64_t>(cd.tile_begin + i) * kPart;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
     }
-    if (lane == 0 && cd.edge_tile >= 0) {
+    if (tid == 0 && cd.edge_tile >= 0) {
         const double* pp = A.partials + static_cast<int64_t>(cd.edge_tile) * kPart;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
     }
-    double tot[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const Comp r = wave_comp_sum(acc[q]);
+        if (lane == 0) part[wv][q] = r;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double tot[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Comp r = part[0][q];
+        for (int w = 1; w < NW; ++w) r = comp_merge(r, part[w][q]);
         tot[q] = r.s + r.c;
     }
-    if (lane != 0) return;
 
     const rsv_theta th = A.theta[c];
     bool use_prop = false;
     if (A.do_metropolis) {
 #pragma clang fp contract(off)
         const double dH = tot[kPartDH];
-        double lu;
-        if (A.log_u) {
-            lu = A.log_u[c];
-        } else {
-            double u[4];
-            uniforms4(A.seed, 0, A.sweep, static_cast<uint64_t>(c), kTagAccept, u);
-            lu = log(u[0]);
-        }
+        const double lu = A.log_u ? A.log_u[c] : draws.log_u_accept;
         const bool finite = isfinite(dH);
         const bool accept = finite && (lu < -dH);
         if (!finite) atomicAdd(&A.counters[kCntNonfiniteDH], 1u);
         use_prop = accept;
-        A.accept_ws[c] = accept ? 1 : 0;
+        if (accept) A.state_sel[c] ^= 1;
         if (A.delta_h_out) A.delta_h_out[c] = dH;
         if (A.accepted_out) A.accepted_out[c] = accept ? 1 : 0;
     }
@@ -424,8 +520,7 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs A) {
     rsv_theta out = th;
     if (A.do_theta) {
         bool ran_out = false;
-        const ThetaStream rs{A.seed, A.sweep, static_cast<uint64_t>(c)};
-        out = gibbs_theta(st, static_cast<double>(cd.T), th, A.prior, A.terms, rs, ran_out);
+        out = gibbs_theta(st, static_cast<double>(cd.T), th, A.prior, A.terms, draws, ran_out);
         if (ran_out) atomicAdd(&A.counters[kCntGammaExhausted], 1u);
         A.theta[c] = out;
     }
@@ -433,23 +528,36 @@ __global__ __launch_bounds__(64) void k_finalize(FinalizeArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Commit accepted proposals into the state (and copy h to a trace).
+// State movement between the two buffers (one chain per grid row).
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(256) void k_commit(const ChainDesc* chains, const int32_t* acc,
-                                                const R* h_prop, R* h_cur, R* h_trace) {
+__global__ __launch_bounds__(256) void k_gather_state(const ChainDesc* chains,
+                                                      const int32_t* state_sel, const R* h_a,
+                                                      const R* h_b, R* h_dst) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
-    const bool take = acc[c] != 0;
-    if (!take && !h_trace) return;
+    const R* src = state_sel[c] ? h_b : h_a;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
-         t += stride) {
-        const int64_t i = cd.h_off + t;
-        const R v = take ? h_prop[i] : h_cur[i];
-        if (take) h_cur[i] = v;
-        if (h_trace) h_trace[i] = v;
-    }
+         t += stride)
+        h_dst[cd.h_off + t] = src[cd.h_off + t];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_settle(const ChainDesc* chains, const int32_t* state_sel,
+                                                R* h_a, const R* h_b) {
+    const int c = blockIdx.y;
+    if (!state_sel[c]) return;
+    const ChainDesc cd = chains[c];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
+         t += stride)
+        h_a[cd.h_off + t] = h_b[cd.h_off + t];
+}
+
+__global__ void k_clear_sel(int32_t* state_sel, int32_t n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) state_sel[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -504,47 +612,48 @@ inline int grid_for(int64_t n, int block, int cap) {
     return static_cast<int>(g > cap ? cap : g);
 }
 
-template <typename R, int S>
-hipError_t launch_traj_t(hipStream_t st, bool mass, bool edge, bool ret, const TrajArgs<R>& a) {
+template <typename R, int S, int NW>
+hipError_t launch_traj_t(hipStream_t st, bool mass, bool ret, const TrajArgs<R>& a) {
     if (a.n_list <= 0) return hipSuccess;
-    const dim3 grid((a.n_list + 3) / 4), block(256);
-#define RSV_TRAJ(M, E, RT) hipLaunchKernelGGL((k_traj<R, S, M, E, RT>), grid, block, 0, st, a)
-    if (ret) {
-        if (mass) { if (edge) RSV_TRAJ(true, true, true); else RSV_TRAJ(true, false, true); }
-        else      { if (edge) RSV_TRAJ(false, true, true); else RSV_TRAJ(false, false, true); }
-    } else {
-        if (mass) { if (edge) RSV_TRAJ(true, true, false); else RSV_TRAJ(true, false, false); }
-        else      { if (edge) RSV_TRAJ(false, true, false); else RSV_TRAJ(false, false, false); }
-    }
+    constexpr int per_block = 4 / NW;
+    const dim3 grid((a.n_list + per_block - 1) / per_block), block(256);
+#define RSV_TRAJ(M, RT) hipLaunchKernelGGL((k_traj<R, S, NW, M, RT>), grid, block, 0, st, a)
+    if (ret) { if (mass) RSV_TRAJ(true, true); else RSV_TRAJ(false, true); }
+    else     { if (mass) RSV_TRAJ(true, false); else RSV_TRAJ(false, false); }
 #undef RSV_TRAJ
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Sites per lane of the trajectory kernel: the compiled choices per
-// precision, the first being the default.
-int traj_sites_per_lane(int precision, int requested) {
-    if (precision == RSV_F64) {
-        if (requested == 0) return 8;
-        return (requested == 8 || requested == 16) ? requested : -1;
-    }
-    if (requested == 0) return 16;
-    return (requested == 16 || requested == 32) ? requested : -1;
+// Tile shapes compiled for each precision: (sites per lane, wavefronts per
+// tile); the first is the default.
+bool traj_shape_available(int precision, int S, int NW) {
+    if (NW != 1 && NW != 4) return false;
+    return precision == RSV_F64 ? (S == 4 || S == 8) : (S == 8 || S == 16);
+}
+void traj_default_shape(int precision, int* S, int* NW) {
+    *S = 8;
+    *NW = 4;
+    (void)precision;
 }
 
-hipError_t launch_traj(hipStream_t st, int precision, int S, bool mass, bool edge,
+hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
                        const void* args) {
     if (precision == RSV_F64) {
         const auto& a = *static_cast<const TrajArgs<double>*>(args);
         const bool ret = (a.terms & RSV_TERM_RETURN) != 0;
-        if (S == 8) return launch_traj_t<double, 8>(st, mass, edge, ret, a);
-        if (S == 16) return launch_traj_t<double, 16>(st, mass, edge, ret, a);
+        if (S == 4 && NW == 1) return launch_traj_t<double, 4, 1>(st, mass, ret, a);
+        if (S == 4 && NW == 4) return launch_traj_t<double, 4, 4>(st, mass, ret, a);
+        if (S == 8 && NW == 1) return launch_traj_t<double, 8, 1>(st, mass, ret, a);
+        if (S == 8 && NW == 4) return launch_traj_t<double, 8, 4>(st, mass, ret, a);
     } else {
         const auto& a = *static_cast<const TrajArgs<float>*>(args);
         const bool ret = (a.terms & RSV_TERM_RETURN) != 0;
-        if (S == 16) return launch_traj_t<float, 16>(st, mass, edge, ret, a);
-        if (S == 32) return launch_traj_t<float, 32>(st, mass, edge, ret, a);
+        if (S == 8 && NW == 1) return launch_traj_t<float, 8, 1>(st, mass, ret, a);
+        if (S == 8 && NW == 4) return launch_traj_t<float, 8, 4>(st, mass, ret, a);
+        if (S == 16 && NW == 1) return launch_traj_t<float, 16, 1>(st, mass, ret, a);
+        if (S == 16 && NW == 4) return launch_traj_t<float, 16, 4>(st, mass, ret, a);
     }
     return hipErrorInvalidValue;
 }
@@ -580,37 +689,58 @@ hipError_t launch_validate(hipStream_t st, const double* y, const double* lrv, i
     return launch_count_nonfinite(st, h, n_state, precision, counters + kCntNonfiniteState);
 }
 
-hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a) {
-    hipLaunchKernelGGL(k_finalize, dim3(a.n_chains), dim3(64), 0, st, a);
+hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain) {
+    // 256 threads at most: wider blocks would cap the registers below the 11
+    // compensated accumulators each thread keeps, and spill them
+    if (max_tiles_per_chain <= 128)
+        hipLaunchKernelGGL(k_finalize<64>, dim3(a.n_chains), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_finalize<256>, dim3(a.n_chains), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_commit(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
-                         const int32_t* accept_ws, const void* h_prop, void* h_cur,
-                         void* h_trace, int precision) {
+hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
+                               int32_t max_T, const int32_t* state_sel, const void* h_a,
+                               const void* h_b, void* h_dst, int precision) {
     const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
     if (precision == RSV_F64)
-        hipLaunchKernelGGL(k_commit<double>, g, b, 0, st, chains, accept_ws,
-                           static_cast<const double*>(h_prop), static_cast<double*>(h_cur),
-                           static_cast<double*>(h_trace));
+        hipLaunchKernelGGL(k_gather_state<double>, g, b, 0, st, chains, state_sel,
+                           static_cast<const double*>(h_a), static_cast<const double*>(h_b),
+                           static_cast<double*>(h_dst));
     else
-        hipLaunchKernelGGL(k_commit<float>, g, b, 0, st, chains, accept_ws,
-                           static_cast<const float*>(h_prop), static_cast<float*>(h_cur),
-                           static_cast<float*>(h_trace));
+        hipLaunchKernelGGL(k_gather_state<float>, g, b, 0, st, chains, state_sel,
+                           static_cast<const float*>(h_a), static_cast<const float*>(h_b),
+                           static_cast<float*>(h_dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
+                         int32_t* state_sel, void* h_a, const void* h_b, int precision) {
+    const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
+    if (precision == RSV_F64)
+        hipLaunchKernelGGL(k_settle<double>, g, b, 0, st, chains, state_sel,
+                           static_cast<double*>(h_a), static_cast<const double*>(h_b));
+    else
+        hipLaunchKernelGGL(k_settle<float>, g, b, 0, st, chains, state_sel,
+                           static_cast<float*>(h_a), static_cast<const float*>(h_b));
+    hipLaunchKernelGGL(k_clear_sel, dim3((n_chains + 255) / 256), dim3(256), 0, st, state_sel,
+                       n_chains);
     return hipGetLastError();
 }
 
 hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
-                        const ChainDesc* chains, const rsv_theta* theta, const void* h_cur,
-                        const double* lrv_d, double* partials, double* chain_edge,
-                        int precision) {
+                        const ChainDesc* chains, const rsv_theta* theta, const void* h_a,
+                        const void* h_b, const int32_t* state_sel, const double* lrv_d,
+                        double* partials, double* chain_edge, int precision) {
     const dim3 g((n_tiles + 3) / 4), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_stats<double>, g, b, 0, st, tiles, n_tiles, chains, theta,
-                           static_cast<const double*>(h_cur), lrv_d, partials, chain_edge);
+                           static_cast<const double*>(h_a), static_cast<const double*>(h_b),
+                           state_sel, lrv_d, partials, chain_edge);
     else
         hipLaunchKernelGGL(k_stats<float>, g, b, 0, st, tiles, n_tiles, chains, theta,
-                           static_cast<const float*>(h_cur), lrv_d, partials, chain_edge);
+                           static_cast<const float*>(h_a), static_cast<const float*>(h_b),
+                           state_sel, lrv_d, partials, chain_edge);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 """Instruction counts of the leapfrog loop, read from the gfx950 assembly.
 
 Compiles csrc/rsv_kernels.hip to device assembly, finds in each trajectory
-kernel (identity mass, body tiles, RSV terms) the loop that carries the DPP
+kernel (identity mass, RSV terms) the loop that carries the DPP
 lane shifts -- one leapfrog step over a lane's S sites -- and counts its VALU
 instructions.  Dividing by S gives VALU instructions per site-update, the
 per-unit figure of the ALU roofline.  Writes isa_counts.json next to this file.
@@ -17,8 +17,10 @@ from collections import Counter
 from . import build as B
 
 OUT = os.path.join(B.PKG, "isa_counts.json")
-VARIANTS = {("f64", 8): "IdLi8ELb0ELb0ELb1E", ("f64", 16): "IdLi16ELb0ELb0ELb1E",
-            ("f32", 16): "IfLi16ELb0ELb0ELb1E", ("f32", 32): "IfLi32ELb0ELb0ELb1E"}
+VARIANTS = {("f64", 4, 1): "IdLi4ELi1ELb0ELb1E", ("f64", 4, 4): "IdLi4ELi4ELb0ELb1E",
+            ("f64", 8, 1): "IdLi8ELi1ELb0ELb1E", ("f64", 8, 4): "IdLi8ELi4ELb0ELb1E",
+            ("f32", 8, 1): "IfLi8ELi1ELb0ELb1E", ("f32", 8, 4): "IfLi8ELi4ELb0ELb1E",
+            ("f32", 16, 1): "IfLi16ELi1ELb0ELb1E", ("f32", 16, 4): "IfLi16ELi4ELb0ELb1E"}
 
 
 def assemble() -> str:
@@ -37,7 +39,7 @@ def kernel_text(asm: str, tag: str) -> str:
     if not m:
         raise KeyError(tag)
     body = asm[m.end():]
-    return body[: body.index("s_endpgm")], m.group(1)
+    return body[: body.index(".Lfunc_end")], m.group(1)
 
 
 def descriptor(asm: str, name: str) -> dict:
@@ -47,7 +49,7 @@ def descriptor(asm: str, name: str) -> dict:
             "scratch_bytes": get("amdhsa_private_segment_fixed_size")}
 
 
-def leapfrog_loop(text: str):
+def leapfrog_loop(text: str, n_dpp: int):
     lines = [l.strip() for l in text.split("\n")]
     labels = {}
     for i, l in enumerate(lines):
@@ -61,22 +63,27 @@ def leapfrog_loop(text: str):
         if tgt in labels and labels[tgt] < i:
             seg = [x for x in lines[labels[tgt]:i + 1]
                    if x and not x.startswith((";", ".")) and not x.endswith(":")]
-            if any("_dpp" in x for x in seg) and (best is None or len(seg) > len(best)):
+            # the innermost loop that carries one step's lane shifts
+            if sum("_dpp" in x for x in seg) >= n_dpp and (best is None or len(seg) < len(best)):
                 best = seg
     return Counter(x.split()[0] for x in best)
 
 
 def count(asm: str) -> dict:
     table = {}
-    for (prec, S), tag in VARIANTS.items():
+    for (prec, S, NW), tag in VARIANTS.items():
         text, name = kernel_text(asm, tag)
-        ops = leapfrog_loop(text)
+        ops = leapfrog_loop(text, 4 if prec == "f64" else 2)
         valu = sum(v for k, v in ops.items() if k.startswith("v_"))
         fp = sum(v for k, v in ops.items() if k.startswith("v_") and prec in k)
-        table[f"{prec}_S{S}"] = dict(
-            loop_instructions=sum(ops.values()), valu_per_site_update=valu / S,
-            fp_valu_per_site_update=fp / S, **descriptor(asm, name),
-            top_ops=dict(ops.most_common(12)))
+        # each leapfrog step shifts two values between lanes: 2 DPP moves per
+        # 32-bit word, so the loop body holds `steps` unrolled steps
+        dpp = sum(v for k, v in ops.items() if "_dpp" in k)
+        steps = dpp // (4 if prec == "f64" else 2)
+        table[f"{prec}_S{S}_W{NW}"] = dict(
+            loop_instructions=sum(ops.values()), steps_per_loop=steps,
+            valu_per_site_update=valu / (S * steps), fp_valu_per_site_update=fp / (S * steps),
+            **descriptor(asm, name), top_ops=dict(ops.most_common(12)))
     return table
 
 

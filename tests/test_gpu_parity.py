@@ -42,13 +42,13 @@ def state_from(hs, C, jitter=0.0, seed=0):
 
 
 def sampler(Ts, C=1, seed=5, k=20, precision=RSV_F64, thetas=None, log_mass=None, S=0,
-            terms=3, jitter=0.05):
+            terms=3, jitter=0.05, NW=0):
     offsets, ys, rs, hs = make_series(Ts, 100 + seed, thetas)
     h0 = state_from(hs, C, jitter)
     th = [thetas[s] if thetas else TH for s in range(len(Ts)) for _ in range(C)]
     smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                          chains_per_series=C, precision=precision, max_steps=k, seed=seed,
-                         log_mass=log_mass, sites_per_lane=S, terms=terms)
+                         log_mass=log_mass, sites_per_lane=S, waves_per_tile=NW, terms=terms)
     return smp, offsets, ys, rs, h0, th
 
 
@@ -76,9 +76,9 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("Ts,C,k,dt", SHAPES)
-@pytest.mark.parametrize("S", [8, 16])
-def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S):
-    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S)
+@pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 4), (8, 4)])
+def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW)
     rng = np.random.default_rng(3)
     p0 = rng.standard_normal(h0.size)
     log_u = np.log(rng.uniform(size=smp.n_chains))
