@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -46,6 +48,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--workload", choices=["long", "small", "batched"], default="long",
+                    help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
+                         "batched: 512 series x 4 chains, FP32-mixed")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (for counter calibration)")
     return ap.parse_args()
 
 
@@ -95,12 +102,172 @@ def cpu_baseline(y, lr, h0, theta, k, dtau, n_sweeps, seed, T):
             "seconds": dt}
 
 
+def min_ess_from_traces(h_trace, theta_trace):
+    from paper_1603_08114_amd import diagnostics
+    ess_h = diagnostics.ess_geyer(h_trace)
+    ess_th = diagnostics.ess_geyer(theta_trace)
+    return float(min(np.nanmin(ess_h), np.nanmin(ess_th))), ess_h, ess_th
+
+
+def run_small(args):
+    """Single series, T = 1000, k = 20, dtau = 0.05, 500 burn-in + 5000 sweeps,
+    theta every sweep, FP64: min over {h_t} and theta of the ESS per second."""
+    import torch
+    import synth
+    from paper_1603_08114_amd import api
+    T, k, dtau, burn, n = 1000, 20, 0.05, 500, 5000
+    theta = dict(synth.THETA_STAR)
+    y, lr, h_true = synth.simulate_rsv(T, theta, 1)
+    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1)
+    smp.sweep(0, burn, (k, dtau), update_theta=True, record=())
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(smp.stream)
+    out = smp.sweep(burn, n, (k, dtau), update_theta=True, record=("theta", "accepted"),
+                    record_h=True)
+    ev1.record(smp.stream)
+    torch.cuda.synchronize()
+    elapsed = ev0.elapsed_time(ev1) / 1e3
+    min_ess, ess_h, ess_th = min_ess_from_traces(out["h"].cpu().numpy(),
+                                                 out["theta"][:, 0].cpu().numpy())
+    res = {"metric": METRIC, "value": min_ess / elapsed, "unit": "min-ESS/s", "n_gpus": 1,
+           "steps": n, "warmup": burn, "ms_per_step": elapsed / n * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": "single-series RSV HMC, T=1000, k=20, dtau=0.05, FP64, "
+                                  "500 burn-in + 5000 sweeps, theta every sweep",
+                      "T": T, "k": k, "dtau": dtau, "chains": 1},
+           "site_updates_per_s": T * k * n / elapsed, "min_ess": min_ess,
+           "min_ess_theta": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
+                                     map(float, ess_th))),
+           "acceptance": float(out["accepted"].float().mean().item())}
+    if args.cpu_sweeps > 0:
+        import time as _t
+        import oracle
+        t0 = _t.perf_counter()
+        ref = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True)
+        dt = _t.perf_counter() - t0
+        m_ref, _, _ = min_ess_from_traces(ref["h_trace"][burn:], ref["theta_trace"][burn:])
+        res["cpu_baseline"] = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "the whole run (500 + 5000 sweeps), serial C; time "
+                                         "pro-rated to the 5000 measured sweeps",
+                               "site_updates_per_s": T * k * (burn + n) / dt, "seconds": dt}
+    return res
+
+
+def run_batched(args):
+    """512 series, T ~ U{500..8000}, per-series theta, 4 chains each, k = 30,
+    FP32-mixed leapfrog; per-series dtau adapted to ~0.8 acceptance over 500
+    warm-up sweeps; 2000 measured sweeps with batch means (50 batches of 40)
+    accumulated on the device.  value = median over series of min-ESS/s."""
+    import torch
+    import synth
+    from paper_1603_08114_amd import api, diagnostics
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED
+    S_, C_, k = 512, 4, 30
+    data = synth.make_batch(S_, 500, 8000, seed=3)
+    off = data["offsets"]
+    Ts = np.diff(off)
+    h0 = np.concatenate([np.tile(data["h_true"][off[s]:off[s + 1]], C_) for s in range(S_)])
+    thetas = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
+    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, chains_per_series=C_,
+                         precision=RSV_F32_MIXED, max_steps=k, seed=3)
+    dtau = 0.05 * (1000.0 / Ts) ** 0.25
+    sweep = 0
+    for _ in range(10):  # 10 windows of 50 warm-up sweeps
+        out = smp.sweep(sweep, 50, [(k, d) for d in dtau], update_theta=True,
+                        record=("delta_h",))
+        sweep += 50
+        dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
+        acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
+        dtau = dtau * np.exp(1.5 * (acc - 0.8))
+    lf = [(k, d) for d in dtau]
+    smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
+    sweep += 1
+    torch.cuda.synchronize()
+    n, bl = 2000, 40
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(smp.stream)
+    out = smp.sweep(sweep, n, lf, update_theta=True, record=("theta", "accepted"), batch_len=bl)
+    ev1.record(smp.stream)
+    torch.cuda.synchronize()
+    elapsed = ev0.elapsed_time(ev1) / 1e3
+    bsum = out["h_batch_sum"].cpu().numpy() / bl
+    sq = out["h_sq_sum"].cpu().numpy() / n
+    mean = bsum.mean(axis=0)
+    var = np.maximum(sq - mean * mean, 0.0)
+    ess_site = diagnostics.ess_batch_means(bsum, var, n)
+    th = out["theta"].cpu().numpy()  # (n, chains, 5)
+    per_series = np.empty(S_)
+    for s in range(S_):
+        e_h = 0.0
+        e_th = np.zeros(5)
+        T = int(Ts[s])
+        for j in range(C_):
+            c = s * C_ + j
+            start = C_ * int(off[s]) + j * T
+            e_h = e_h + ess_site[start:start + T]
+            e_th += diagnostics.ess_geyer(th[:, c, :])
+        per_series[s] = min(np.nanmin(e_h), np.nanmin(e_th))
+    rate = per_series / elapsed
+    total_su = float(Ts.sum()) * C_ * k * n
+    res = {"metric": METRIC, "value": float(np.median(rate)), "unit": "min-ESS/s (median over series)",
+           "n_gpus": 1, "steps": n, "warmup": 500, "ms_per_step": elapsed / n * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32-mixed", "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": "batched RSV HMC: 512 series, T~U{500..8000}, 4 chains each, "
+                                  "k=30, FP32 leapfrog, FP64 dH/theta, 2000 sweeps",
+                      "series": S_, "chains_per_series": C_, "k": k, "total_sites": int(Ts.sum())},
+           "min_over_series": float(rate.min()), "site_updates_per_s": total_su / elapsed,
+           "acceptance": float(out["accepted"].float().mean().item()),
+           "dtau_range": [float(dtau.min()), float(dtau.max())]}
+    if args.cpu_sweeps > 0:
+        import time as _t
+        import oracle
+        s = int(np.argsort(Ts)[S_ // 2])
+        T = int(Ts[s])
+        y2 = data["y"][off[s]:off[s + 1]] ** 2
+        r = data["log_rv"][off[s]:off[s + 1]]
+        t0 = _t.perf_counter()
+        for j in range(C_):
+            oracle.run(data["h_true"][off[s]:off[s + 1]], data["thetas"][s], y2, r, k,
+                       float(dtau[s]), 25, seed=3, chain=s * C_ + j)
+        dt = _t.perf_counter() - t0
+        res["cpu_baseline"] = {"value": T * k * 25 * C_ / dt, "unit": "site-updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"4 chains x 25 sweeps of the median-length series "
+                                         f"(T={T}), FP64 serial C", "seconds": dt}
+    return res
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of 256 MiB (the FETCH_SIZE / WRITE_SIZE
+    reference: each copy reads and writes exactly 256 MiB)."""
+    import torch
+    a = torch.empty(1 << 25, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_per_copy": a.numel() * 8, "copies": 5}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design in DESIGN.md, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.workload != "long":
+        res = run_small(args) if args.workload == "small" else run_batched(args)
+        print(json.dumps(res), flush=True)
+        return
     import numpy as np
     import torch
 

@@ -109,6 +109,13 @@ typedef struct {
     rsv_theta *theta;    /* device, n_sweeps * n_chains, theta after the sweep */
     void *h;             /* device, n_sweeps * n_state, h after the sweep, in the
                             state precision (FP64 or FP32)                      */
+    /* Moment accumulators for runs too long to store (batch means): after
+     * sweep i of the call, h is added to h_batch_sum[(i / batch_len) * n_state
+     * + site] and h^2 to h_sq_sum[site] (FP64; the caller zeroes them). */
+    double *h_batch_sum; /* device, ceil(n_sweeps / batch_len) * n_state, or NULL */
+    double *h_sq_sum;    /* device, n_state, or NULL                            */
+    int32_t batch_len;   /* sweeps per batch (>= 1 when h_batch_sum is set)    */
+    int32_t reserved;
 } rsv_trace;
 
 typedef struct rsv_ctx rsv_ctx;

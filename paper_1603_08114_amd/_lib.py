@@ -57,7 +57,8 @@ class rsv_problem(C.Structure):
 
 class rsv_trace(C.Structure):
     _fields_ = [("delta_h", C.c_void_p), ("accepted", C.c_void_p), ("theta", C.c_void_p),
-                ("h", C.c_void_p)]
+                ("h", C.c_void_p), ("h_batch_sum", C.c_void_p), ("h_sq_sum", C.c_void_p),
+                ("batch_len", C.c_int32), ("reserved", C.c_int32)]
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:

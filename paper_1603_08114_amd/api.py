@@ -259,10 +259,21 @@ class RSVSampler:
 
     def sweep(self, first_sweep, n_sweeps, lf, update_theta=True, record=("delta_h", "accepted",
                                                                               "theta"),
-              record_h=False):
+              record_h=False, batch_len=0):
+        """n sweeps; ``record`` names per-sweep traces to return, ``record_h``
+        stores h after every sweep, ``batch_len`` > 0 accumulates batch sums of
+        h (and the sum of h^2) on the device instead."""
         n, nc = int(n_sweeps), self.n_chains
         out = {}
         tr = L.rsv_trace()
+        if batch_len:
+            nb = (n + batch_len - 1) // batch_len
+            out["h_batch_sum"] = torch.zeros((nb, self.n_state), dtype=torch.float64,
+                                             device=self.device)
+            out["h_sq_sum"] = torch.zeros(self.n_state, dtype=torch.float64, device=self.device)
+            tr.h_batch_sum = out["h_batch_sum"].data_ptr()
+            tr.h_sq_sum = out["h_sq_sum"].data_ptr()
+            tr.batch_len = int(batch_len)
         if "delta_h" in record:
             out["delta_h"] = torch.empty((n, nc), dtype=torch.float64, device=self.device)
             tr.delta_h = out["delta_h"].data_ptr()

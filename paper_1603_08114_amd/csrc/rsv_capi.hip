@@ -510,6 +510,8 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
                          const rsv_leapfrog* lf, int32_t update_theta, const rsv_trace* trace) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
     if (n_sweeps < 0) return fail(RSV_EINVAL, "n_sweeps must be >= 0");
+    if (trace && trace->h_batch_sum && trace->batch_len < 1)
+        return fail(RSV_EINVAL, "batch_len must be >= 1 with h_batch_sum");
     rsv_status st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
     const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
@@ -524,6 +526,13 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
                             update_theta ? 1 : 0, tt, ht, nullptr);
         if (st != RSV_OK) return st;
+        if (trace && (trace->h_batch_sum || trace->h_sq_sum)) {
+            double* bs = trace->h_batch_sum
+                             ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
+                             : nullptr;
+            RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
+                                      c->h_prop, bs, trace->h_sq_sum, c->pb.precision));
+        }
     }
     return settle(c);
 }

@@ -104,6 +104,10 @@ hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_ti
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,
                                const void* h_b, void* h_dst, int precision);
+// Add every chain's current state to batch_sum (and its square to sq_sum).
+hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
+                             int32_t max_T, const int32_t* state_sel, const void* h_a,
+                             const void* h_b, double* batch_sum, double* sq_sum, int precision);
 // Move chains whose current state is in h_b back into h_a and clear state_sel.
 hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
                          int32_t* state_sel, void* h_a, const void* h_b, int precision);

@@ -544,6 +544,24 @@ __global__ __launch_bounds__(256) void k_gather_state(const ChainDesc* chains,
 }
 
 template <typename R>
+__global__ __launch_bounds__(256) void k_accumulate(const ChainDesc* chains,
+                                                    const int32_t* state_sel, const R* h_a,
+                                                    const R* h_b, double* batch_sum,
+                                                    double* sq_sum) {
+    const int c = blockIdx.y;
+    const ChainDesc cd = chains[c];
+    const R* src = state_sel[c] ? h_b : h_a;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
+         t += stride) {
+        const int64_t i = cd.h_off + t;
+        const double v = static_cast<double>(src[i]);
+        if (batch_sum) batch_sum[i] += v;
+        if (sq_sum) sq_sum[i] += v * v;
+    }
+}
+
+template <typename R>
 __global__ __launch_bounds__(256) void k_settle(const ChainDesc* chains, const int32_t* state_sel,
                                                 R* h_a, const R* h_b) {
     const int c = blockIdx.y;
@@ -711,6 +729,21 @@ hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t 
         hipLaunchKernelGGL(k_gather_state<float>, g, b, 0, st, chains, state_sel,
                            static_cast<const float*>(h_a), static_cast<const float*>(h_b),
                            static_cast<float*>(h_dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
+                             int32_t max_T, const int32_t* state_sel, const void* h_a,
+                             const void* h_b, double* batch_sum, double* sq_sum, int precision) {
+    const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
+    if (precision == RSV_F64)
+        hipLaunchKernelGGL(k_accumulate<double>, g, b, 0, st, chains, state_sel,
+                           static_cast<const double*>(h_a), static_cast<const double*>(h_b),
+                           batch_sum, sq_sum);
+    else
+        hipLaunchKernelGGL(k_accumulate<float>, g, b, 0, st, chains, state_sel,
+                           static_cast<const float*>(h_a), static_cast<const float*>(h_b),
+                           batch_sum, sq_sum);
     return hipGetLastError();
 }
 

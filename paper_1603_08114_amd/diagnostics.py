@@ -1,0 +1,72 @@
+"""Effective sample size and Monte Carlo standard errors of MCMC output.
+
+Host-side analysis of chains produced by the sampler (numpy only):
+
+* ``ess_geyer`` -- Geyer's initial monotone sequence estimator (Geyer 1992,
+  "Practical Markov chain Monte Carlo", Statist. Sci. 7): autocovariances by
+  FFT, sums of adjacent pairs Gamma_k = gamma_{2k} + gamma_{2k+1} truncated at
+  the first non-positive pair and forced monotone; tau = -1 + 2 sum Gamma_k.
+* ``ess_batch_means`` -- from the means of b non-overlapping batches (for
+  runs too long to store, accumulated on the device).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _autocov(x: np.ndarray) -> np.ndarray:
+    """Autocovariances (biased, divided by n) of each column, lags 0..n-1."""
+    n = x.shape[0]
+    xc = x - x.mean(axis=0)
+    m = 1 << int(np.ceil(np.log2(2 * n)))
+    f = np.fft.rfft(xc, n=m, axis=0)
+    ac = np.fft.irfft(f * np.conj(f), n=m, axis=0)[:n]
+    return ac / n
+
+
+def integrated_time(x) -> np.ndarray:
+    """Integrated autocorrelation time of each column (initial monotone sequence)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    n, d = x.shape
+    g = _autocov(x)
+    tau = np.empty(d)
+    for j in range(d):
+        g0 = g[0, j]
+        if g0 <= 0:
+            tau[j] = np.nan
+            continue
+        npair = (n - 1) // 2
+        pairs = g[0:2 * npair:2, j] + g[1:2 * npair + 1:2, j]
+        pos = np.nonzero(pairs <= 0)[0]
+        m = pos[0] if pos.size else npair
+        p = np.minimum.accumulate(pairs[:m]) if m > 0 else pairs[:0]
+        tau[j] = (-g0 + 2.0 * p.sum()) / g0
+        tau[j] = max(tau[j], 1.0 / n)
+    return tau
+
+
+def ess_geyer(x) -> np.ndarray:
+    """ESS of each column of draws x (n, d) or (n,)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    return n / integrated_time(x)
+
+
+def ess_batch_means(batch_means, variance, n_draws: int) -> np.ndarray:
+    """ESS from b batch means (b, d) of equal-length batches, the variance of
+    the draws (d,) and the number of draws: ESS = var / MCSE^2 with
+    MCSE^2 = var(batch means) / b."""
+    bm = np.asarray(batch_means, dtype=np.float64)
+    b = bm.shape[0]
+    s2 = bm.var(axis=0, ddof=1)
+    mcse2 = s2 / b
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ess = np.asarray(variance) / mcse2
+    return np.minimum(ess, n_draws * 10.0)
+
+
+def mcse_mean(x) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    return np.sqrt(x.var(axis=0) / ess_geyer(x))

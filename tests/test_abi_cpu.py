@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_lib.rsv_prior) == 64
     assert C.sizeof(_lib.rsv_leapfrog) == 16
     assert C.sizeof(_lib.rsv_problem) == 4 + 4 + 8 * 3 + 4 * 6 + 8 + 64
-    assert C.sizeof(_lib.rsv_trace) == 32
+    assert C.sizeof(_lib.rsv_trace) == 56
 
 
 def _pb(offsets, **kw):

@@ -1,0 +1,42 @@
+"""ESS estimators against AR(1) series of known integrated autocorrelation
+time tau = (1 + rho) / (1 - rho)."""
+import numpy as np
+import pytest
+from scipy.signal import lfilter
+
+from paper_1603_08114_amd import diagnostics as D
+
+
+def ar1(n, rho, d, seed):
+    rng = np.random.default_rng(seed)
+    e = rng.standard_normal((n, d))
+    x = lfilter([1.0], [1.0, -rho], e, axis=0)
+    return x[1000:]
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.5, 0.9, 0.99])
+def test_geyer_integrated_time_ar1(rho):
+    tau_true = (1 + rho) / (1 - rho)
+    x = ar1(400_000 + 1000, rho, 8, seed=int(rho * 100))
+    tau = D.integrated_time(x)
+    assert np.all(np.abs(tau / tau_true - 1) < 0.10), (tau, tau_true)
+
+
+def test_geyer_negative_correlation():
+    # rho < 0: tau < 1, ESS > n (antithetic draws), still estimated
+    x = ar1(200_000 + 1000, -0.5, 4, seed=3)
+    tau = D.integrated_time(x)
+    assert np.all(np.abs(tau / (1 / 3) - 1) < 0.15), tau
+
+
+@pytest.mark.parametrize("rho", [0.5, 0.9])
+def test_batch_means_ess_ar1(rho):
+    n = 400_000
+    x = ar1(n + 1000, rho, 16, seed=11)
+    b = int(np.sqrt(n))
+    m = n // b
+    bm = x[: b * m].reshape(b, m, -1).mean(axis=1)
+    ess = D.ess_batch_means(bm, x.var(axis=0), n)
+    ess_true = n * (1 - rho) / (1 + rho)
+    # batch-means ESS has ~ sqrt(2/b) relative scatter per column
+    assert abs(np.median(ess) / ess_true - 1) < 0.1

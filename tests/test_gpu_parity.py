@@ -274,3 +274,21 @@ def test_poisoned_state_reported_by_check():
     smp.h[5] = float("nan")
     st, _ = smp.check()
     assert st == -5
+
+
+def test_batch_mean_accumulators_match_recorded_trace():
+    k, dt, n, bl = 20, 0.05, 30, 7
+    smp, offsets, ys, rs, h0, th = sampler([700, 1500], 2, k=k)
+    out = smp.sweep(0, n, (k, dt), update_theta=True, record=(), record_h=True, batch_len=bl)
+    h = out["h"].cpu().numpy()
+    bs = out["h_batch_sum"].cpu().numpy()
+    for b in range(bs.shape[0]):
+        ref = np.zeros(h.shape[1])
+        for i in range(b * bl, min(n, (b + 1) * bl)):
+            ref += h[i]
+        np.testing.assert_array_equal(bs[b], ref)
+    sq = np.zeros(h.shape[1])
+    for i in range(n):
+        sq += h[i] * h[i]
+    # the device forms v*v + sum with one FMA rounding
+    np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq, rtol=1e-14)
