@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
-    ap.add_argument("--workload", choices=["long", "small", "batched"], default="long",
+    ap.add_argument("--workload", choices=["long", "small", "batched", "mass"], default="long",
                     help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
                          "batched: 512 series x 4 chains, FP32-mixed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -243,6 +243,77 @@ def run_batched(args):
     return res
 
 
+def run_mass(args):
+    """Learned diagonal mass: train on identity-FP64 chains of 256 series
+    (T ~ U{500..8000}, seed 4), evaluate on 1024 held-out series
+    (T ~ U{1000..16000}, seed 5), 4 chains each, k = 30, against identity
+    mass, same warm-up (500 sweeps, dtau adapted per series) and 1000 measured
+    sweeps per arm.  value = median over series of min-ESS/s, learned mass
+    with FP32-mixed leapfrog; the other arms are reported beside it."""
+    import torch
+    import synth
+    from paper_1603_08114_amd import learned_mass as LM
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+    C, k = 4, 30
+    n_train, n_held = (64, 128) if args.steps < 200 else (256, 1024)
+    train = synth.make_batch(n_train, 500, 8000, seed=4)
+    held = synth.make_batch(n_held, 1000, 16000, seed=5)
+    print(f"[mass] training targets from {n_train} series", file=sys.stderr, flush=True)
+    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000)
+    target = -torch.log(torch.clamp(tr["var"], min=1e-12))
+    net, hist, r2 = LM.train_network(train, target, tr["theta_mean"], epochs=30)
+    print(f"[mass] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, R^2 {r2:.3f}", file=sys.stderr,
+          flush=True)
+    arms = {"identity_f64": (RSV_F64, None), "learned_f32": (RSV_F32_MIXED, net),
+            "identity_f32": (RSV_F32_MIXED, None), "learned_f64": (RSV_F64, net)}
+    out = {}
+    res_arm = {}
+    for name, (prec, nt) in arms.items():
+        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25)
+        res_arm[name] = r
+        per = np.minimum(r["ess_h"], r["ess_theta"]) / r["elapsed"]
+        out[name] = {"median_min_ess_per_s": float(np.median(per)),
+                     "min_min_ess_per_s": float(per.min()),
+                     "median_ess_h_per_s": float(np.median(r["ess_h"] / r["elapsed"])),
+                     "median_ess_theta_per_s": float(np.median(r["ess_theta"] / r["elapsed"])),
+                     "seconds": r["elapsed"], "acceptance": r["acceptance"],
+                     "median_dtau": float(np.median(r["dtau"]))}
+        print(f"[mass] {name}: {out[name]}", file=sys.stderr, flush=True)
+    # posterior means of h_t and theta: learned FP32 arm vs identity FP64 arm
+    a, b = res_arm["identity_f64"], res_arm["learned_f32"]
+    z = ((b["mean"] - a["mean"]) / torch.sqrt(a["mcse2"] + b["mcse2"])).cpu().numpy()
+    z = z[np.isfinite(z)]
+    frac3 = float(np.mean(np.abs(z) > 3))
+    lim = 0.0027 + 3 * np.sqrt(0.0027 * 0.9973 / z.size)
+    from paper_1603_08114_amd import diagnostics
+    tz = []
+    S_ = len(held["offsets"]) - 1
+    for r_ in (a, b):
+        tr_ = r_["theta_trace"].reshape(r_["theta_trace"].shape[0], S_, C, 5)
+        m = tr_.mean(axis=(0, 2))
+        v = np.stack([np.stack([tr_[:, s, j, :].var(0) / diagnostics.ess_geyer(tr_[:, s, j, :])
+                                for j in range(C)]).sum(0) / C ** 2 for s in range(S_)])
+        tz.append((m, v))
+    zt = (tz[1][0] - tz[0][0]) / np.sqrt(tz[0][1] + tz[1][1])
+    gain = out["learned_f32"]["median_min_ess_per_s"] / out["identity_f64"]["median_min_ess_per_s"]
+    res = {"metric": METRIC, "value": out["learned_f32"]["median_min_ess_per_s"],
+           "unit": "min-ESS/s (median over series)", "n_gpus": 1, "steps": 1000, "warmup": 500,
+           "ms_per_step": out["learned_f32"]["seconds"] / 1000 * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed + bf16 network",
+           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": f"learned diagonal mass: train {n_train} series, evaluate "
+                                  f"{n_held} held-out series x 4 chains, k=30",
+                      "train_series": n_train, "held_out_series": n_held, "k": k},
+           "arms": out, "gain_learned_f32_vs_identity_f64": gain,
+           "training": {"loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "r2": r2},
+           "moments_learned_f32_vs_identity_f64": {
+               "h_mean_frac_abs_z_gt_3": frac3, "h_frac_limit": float(lim),
+               "h_max_abs_z": float(np.abs(z).max()), "n_sites": int(z.size),
+               "theta_max_abs_z": float(np.nanmax(np.abs(zt))),
+               "theta_frac_abs_z_gt_3": float(np.mean(np.abs(zt) > 3))}}
+    return res
+
+
 def calibrate_copy():
     """A plain device-to-device copy of 256 MiB (the FETCH_SIZE / WRITE_SIZE
     reference: each copy reads and writes exactly 256 MiB)."""
@@ -265,7 +336,7 @@ def main():
         calibrate_copy()
         return
     if args.workload != "long":
-        res = run_small(args) if args.workload == "small" else run_batched(args)
+        res = {"small": run_small, "batched": run_batched, "mass": run_mass}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     import numpy as np

@@ -22,7 +22,10 @@ PRIOR_KEYS = ("mu_mean", "mu_var", "xi_mean", "xi_var",
 # Every symbol include/rsv_hmc.h declares.
 EXPORTS = ("rsv_hmc_workspace_bytes", "rsv_hmc_state_size", "rsv_hmc_init", "rsv_hmc_momenta",
            "rsv_hmc_trajectory", "rsv_theta_update", "rsv_hmc_sweep", "rsv_hmc_check",
-           "rsv_hmc_profile", "rsv_hmc_kernel_time", "rsv_hmc_destroy", "rsv_last_error")
+           "rsv_hmc_profile", "rsv_hmc_kernel_time", "rsv_hmc_destroy", "rsv_last_error",
+           "rsv_mlp_features", "rsv_mlp_forward", "rsv_mlp_grad_workspace_bytes", "rsv_mlp_grad",
+           "rsv_mlp_adam")
+MLP_INPUTS, MLP_INPUTS_PAD, MLP_HIDDEN, MLP_PARAMS = 27, 32, 64, 6337
 
 
 class rsv_theta(C.Structure):
@@ -82,6 +85,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "rsv_hmc_kernel_time": (C.c_int32, [V, P(C.c_double), P(C.c_int64)]),
         "rsv_hmc_destroy": (C.c_int32, [V]),
         "rsv_last_error": (C.c_char_p, []),
+        "rsv_mlp_features": (C.c_int32, [C.c_int32, V, V, V, V, V, V, C.c_int64, V, V]),
+        "rsv_mlp_forward": (C.c_int32, [C.c_int64, V, V, V, C.c_int32, V]),
+        "rsv_mlp_grad_workspace_bytes": (C.c_size_t, [C.c_int64]),
+        "rsv_mlp_grad": (C.c_int32, [C.c_int64, V, V, V, V, V, V, V, C.c_size_t, V]),
+        "rsv_mlp_adam": (C.c_int32, [V, V, V, V, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                     C.c_float, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

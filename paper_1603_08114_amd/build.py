@@ -6,9 +6,9 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("rsv_kernels.hip", "rsv_capi.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("rsv_kernels.hip", "rsv_capi.hip", "rsv_mlp.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("rsv_device.h", "rsv_exp.h", "rsv_internal.h")] + \
-          [os.path.join(ROOT, "include", "rsv_hmc.h")]
+          [os.path.join(ROOT, "include", f) for f in ("rsv_hmc.h", "rsv_mlp.h")]
 LIB = os.path.join(PKG, "librsvhmc.so")
 ARCH = "gfx950"
 

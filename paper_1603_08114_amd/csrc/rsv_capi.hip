@@ -16,11 +16,20 @@
 #include "rsv_hmc.h"
 #include "rsv_internal.h"
 
+namespace {
+thread_local std::string g_last_error;
+}  // namespace
+
+namespace rsv {
+rsv_status set_error(rsv_status code, const char* where, const char* what) {
+    g_last_error = std::string(where) + ": " + what;
+    return code;
+}
+}  // namespace rsv
+
 using namespace rsv;
 
 namespace {
-
-thread_local std::string g_last_error;
 
 rsv_status fail(rsv_status code, const char* fmt, ...) {
     char buf[512];

@@ -90,6 +90,9 @@ struct FinalizeArgs {
     uint32_t* counters;
 };
 
+// Record the message returned by rsv_last_error() and return `code`.
+rsv_status set_error(rsv_status code, const char* where, const char* what);
+
 // Launchers (rsv_kernels.hip).  Each returns the hipError_t of its launch.
 hipError_t launch_prepare(hipStream_t st, const double* y, const double* lrv, int64_t n,
                           double* y2_d, float* y2_f, float* lrv_f);

@@ -10,13 +10,16 @@ import pytest
 from paper_1603_08114_amd import _lib, api
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rsv_hmc.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rsv_\w+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(rsv_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -78,6 +81,16 @@ def test_invalid_problems_rejected_on_host(bad):
     st = _lib.load().rsv_hmc_init(C.byref(ctx), C.byref(pb.struct()), None, None, None, None,
                                   0, None)
     assert st == _lib.RSV_EINVAL and not ctx.value
+
+
+def test_mlp_host_validation():
+    lib = _lib.load()
+    assert lib.rsv_mlp_grad_workspace_bytes(0) == 0
+    assert lib.rsv_mlp_grad_workspace_bytes(65) == 2 * (_lib.MLP_PARAMS + 1) * 4
+    assert lib.rsv_mlp_forward(0, None, None, None, 0, None) == _lib.RSV_EINVAL
+    assert lib.rsv_mlp_grad(10, None, None, None, None, None, None, None, 0, None) == _lib.RSV_EINVAL
+    assert lib.rsv_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == _lib.RSV_EINVAL
+    assert b"rsv_mlp_adam" in lib.rsv_last_error()
 
 
 def test_null_context_is_a_state_error():
