@@ -48,11 +48,15 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
-    ap.add_argument("--workload", choices=["long", "small", "batched", "mass"], default="long",
+    ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "precision"],
+                    default="long",
                     help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
                          "batched: 512 series x 4 chains, FP32-mixed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (for counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE",
+                                                              "KEY"),
+                    help="print the traffic record from four rocprofv3 counter CSVs")
     return ap.parse_args()
 
 
@@ -87,6 +91,65 @@ def isa_figures(precision, S, NW):
     with open(path) as f:
         table = json.load(f)
     return table.get(f"{precision}_S{S}_W{NW}")
+
+
+KERNEL_SOURCES = ("rsv_kernels.hip", "rsv_device.h", "rsv_exp.h", "rsv_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_traj_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1603_08114_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, S, NW, T, k):
+    """HBM bytes per trajectory-kernel launch from the committed counter
+    summary, if it was taken on the current kernel source and this shape."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    key = f"{precision}_S{S}_W{NW}_T{T}_k{k}"
+    if rec.get("source_sha256") != kernel_source_hash() or key not in rec.get("launches", {}):
+        return None
+    return rec["launches"][key]
+
+
+def summarize_counters(fetch_csv, write_csv, calib_fetch_csv, calib_write_csv, key):
+    """Turn four rocprofv3 --pmc counter CSVs (k_traj FETCH_SIZE / WRITE_SIZE,
+    then the same counters for the 256 MiB copy) into bytes per launch."""
+    import csv
+
+    def per_dispatch(path, counter, name_part):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if name_part in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                vals.setdefault(r["Dispatch_Id"], 0.0)
+                vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return list(vals.values())
+
+    copy_bytes = (1 << 25) * 8
+    cf = per_dispatch(calib_fetch_csv, "FETCH_SIZE", "copy")
+    cw = per_dispatch(calib_write_csv, "WRITE_SIZE", "copy")
+    f_scale = copy_bytes / float(np.median(cf))   # bytes per counter unit
+    w_scale = copy_bytes / float(np.median(cw))
+    kf = per_dispatch(fetch_csv, "FETCH_SIZE", "k_traj")
+    kw = per_dispatch(write_csv, "WRITE_SIZE", "k_traj")
+    rec = {"fetch_bytes": float(np.median(kf)) * f_scale,
+           "write_bytes": float(np.median(kw)) * w_scale,
+           "fetch_scale_bytes_per_unit": f_scale, "write_scale_bytes_per_unit": w_scale,
+           "dispatches": [len(kf), len(kw)]}
+    out = {"source_sha256": kernel_source_hash(), "launches": {key: rec}}
+    if os.path.exists(TRAFFIC_FILE):
+        old = json.load(open(TRAFFIC_FILE))
+        if old.get("source_sha256") == out["source_sha256"]:
+            old["launches"].update(out["launches"])
+            out = old
+    print(json.dumps(out, indent=1))
 
 
 def cpu_baseline(y, lr, h0, theta, k, dtau, n_sweeps, seed, T):
@@ -279,22 +342,22 @@ def run_mass(args):
                      "seconds": r["elapsed"], "acceptance": r["acceptance"],
                      "median_dtau": float(np.median(r["dtau"]))}
         print(f"[mass] {name}: {out[name]}", file=sys.stderr, flush=True)
-    # posterior means of h_t and theta: learned FP32 arm vs identity FP64 arm
-    a, b = res_arm["identity_f64"], res_arm["learned_f32"]
+    # Exactness of the learned-mass FP32 h update: posterior means of h_t with
+    # theta held at each series' generating value, learned FP32 vs identity FP64.
+    # (With theta updated, h_t means inherit theta's slow mixing and short-batch
+    # standard errors are too small to judge them.)
+    fixed = {}
+    for name, (prec, nt, sd) in {"identity_f64": (RSV_F64, None, 6),
+                                 "learned_f32": (RSV_F32_MIXED, net, 7)}.items():
+        fixed[name] = LM.run_arm(held, C, k, prec, nt, seed=sd, warm=500, n=1000, bl=25,
+                                 update_theta=False)
+    a, b = fixed["identity_f64"], fixed["learned_f32"]
     z = ((b["mean"] - a["mean"]) / torch.sqrt(a["mcse2"] + b["mcse2"])).cpu().numpy()
     z = z[np.isfinite(z)]
     frac3 = float(np.mean(np.abs(z) > 3))
     lim = 0.0027 + 3 * np.sqrt(0.0027 * 0.9973 / z.size)
-    from paper_1603_08114_amd import diagnostics
-    tz = []
-    S_ = len(held["offsets"]) - 1
-    for r_ in (a, b):
-        tr_ = r_["theta_trace"].reshape(r_["theta_trace"].shape[0], S_, C, 5)
-        m = tr_.mean(axis=(0, 2))
-        v = np.stack([np.stack([tr_[:, s, j, :].var(0) / diagnostics.ess_geyer(tr_[:, s, j, :])
-                                for j in range(C)]).sum(0) / C ** 2 for s in range(S_)])
-        tz.append((m, v))
-    zt = (tz[1][0] - tz[0][0]) / np.sqrt(tz[0][1] + tz[1][1])
+    print(f"[mass] fixed-theta h means: frac |z|>3 {frac3:.4f} (limit {lim:.4f})",
+          file=sys.stderr, flush=True)
     gain = out["learned_f32"]["median_min_ess_per_s"] / out["identity_f64"]["median_min_ess_per_s"]
     res = {"metric": METRIC, "value": out["learned_f32"]["median_min_ess_per_s"],
            "unit": "min-ESS/s (median over series)", "n_gpus": 1, "steps": 1000, "warmup": 500,
@@ -306,11 +369,86 @@ def run_mass(args):
                       "train_series": n_train, "held_out_series": n_held, "k": k},
            "arms": out, "gain_learned_f32_vs_identity_f64": gain,
            "training": {"loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "r2": r2},
-           "moments_learned_f32_vs_identity_f64": {
-               "h_mean_frac_abs_z_gt_3": frac3, "h_frac_limit": float(lim),
-               "h_max_abs_z": float(np.abs(z).max()), "n_sites": int(z.size),
-               "theta_max_abs_z": float(np.nanmax(np.abs(zt))),
-               "theta_frac_abs_z_gt_3": float(np.mean(np.abs(zt) > 3))}}
+           "fixed_theta_h_means_learned_f32_vs_identity_f64": {
+               "frac_abs_z_gt_3": frac3, "frac_limit": float(lim),
+               "max_abs_z": float(np.abs(z).max()), "n_sites": int(z.size),
+               "ess_h_per_s": {n_: float(np.median(r_["ess_h"] / r_["elapsed"]))
+                               for n_, r_ in fixed.items()}}}
+    return res
+
+
+def run_precision(args):
+    """FP32-mixed leapfrog against FP64 on T = 2^22 (theta of the single-series
+    workload, seed 2, k = 50): every FP32 trajectory has an FP64 shadow
+    trajectory from the identical h0, momenta and ln u; then the posterior
+    means of h_t and theta of an FP32 chain against an FP64 chain (batch
+    means, MCSE units).  value = median |dH_FP32 - dH_FP64|."""
+    import torch
+    import synth
+    from paper_1603_08114_amd import api, diagnostics
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+    T, k = args.T, args.k
+    n = max(args.steps, 50)
+    theta = dict(synth.THETA_STAR)
+    y, lr, h_true = synth.simulate_rsv_long(T, theta, args.seed)
+    s32 = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
+                         precision=RSV_F32_MIXED)
+    s64 = api.RSVSampler([0, T], y, lr, h_true.astype(np.float32).astype(np.float64), theta,
+                         max_steps=k, seed=args.seed, precision=RSV_F64)
+    dtau = args.dtau if args.dtau > 0 else tune_dtau(s64, k, T, 0)[0]
+    lf = (k, dtau)
+    s32.sweep(0, 20, lf, update_theta=True, record=())
+    dA, dB, accA, accB, lus = [], [], [], [], []
+    for i in range(n):
+        sweep = 1000 + i
+        s64.h.copy_(s32.h.to(torch.float64))
+        s64.theta.copy_(s32.theta)
+        p0 = s64.momenta(sweep).to(torch.float32).to(torch.float64)
+        lu = float(np.log(np.random.default_rng(sweep).uniform()))
+        da, aa = s32.trajectory(sweep, lf, p0=p0, log_u=[lu])
+        db, ab = s64.trajectory(sweep, lf, p0=p0, log_u=[lu])
+        s32.theta_update(sweep, want_stats=False)
+        dA.append(da.item()); dB.append(db.item()); accA.append(aa.item()); accB.append(ab.item())
+        lus.append(lu)
+    dA, dB = np.array(dA), np.array(dB)
+    err = np.abs(dA - dB)
+    # independent FP32 and FP64 chains: posterior means of h_t in MCSE units,
+    # theta held at its generating value (the h-conditional mixes in a few
+    # sweeps, so batch-means standard errors are reliable); then theta-updating
+    # chains for the theta means (Geyer standard errors: indicative only, theta
+    # mixes over hundreds of sweeps).
+    n_chain, bl = 10 * n, n // 5
+    stats = []
+    for upd in (False, True):
+        for prec, sd in ((RSV_F32_MIXED, 1), (RSV_F64, 2)):
+            smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k,
+                                 seed=args.seed + sd + (10 if upd else 0), precision=prec)
+            smp.sweep(0, 200, lf, update_theta=upd, record=())
+            o = smp.sweep(200, n_chain, lf, update_theta=upd, record=("theta",), batch_len=bl)
+            bm = o["h_batch_sum"] / bl
+            nb = bm.shape[0]
+            th = o["theta"][:, 0].cpu().numpy()
+            stats.append((bm.mean(0), bm.var(0) / nb, th.mean(0),
+                          th.var(0) / diagnostics.ess_geyer(th) if upd else None))
+            smp.close()
+    z = ((stats[0][0] - stats[1][0]) / torch.sqrt(stats[0][1] + stats[1][1])).cpu().numpy()
+    zt = (stats[2][2] - stats[3][2]) / np.sqrt(stats[2][3] + stats[3][3])
+    lim = 0.0027 + 3 * np.sqrt(0.0027 * 0.9973 / z.size)
+    res = {"metric": METRIC, "value": float(np.median(err)), "unit": "|dH_FP32 - dH_FP64| (median)",
+           "n_gpus": 1, "steps": n, "warmup": 20, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed vs f64",
+           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": f"precision study, T={T}, k={k}, FP32-mixed leapfrog vs FP64 "
+                                  f"shadow trajectories", "T": T, "k": k, "dtau": dtau},
+           "dH_abs_error": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
+                            "max": float(err.max()), "median_abs_dH": float(np.median(np.abs(dB)))},
+           "decision_disagreements": int(np.sum(np.array(accA) != np.array(accB))),
+           "trajectories": n,
+           "moments_fp32_vs_fp64_chains": {"sweeps": n_chain, "h_theta": "fixed at generating value",
+                                           "h_frac_abs_z_gt_3": float(np.mean(np.abs(z) > 3)),
+                                           "h_frac_limit": float(lim), "h_max_abs_z": float(np.abs(z).max()),
+                                           "theta_z_indicative": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
+                                                               map(float, zt)))}}
     return res
 
 
@@ -335,8 +473,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.workload != "long":
-        res = {"small": run_small, "batched": run_batched, "mass": run_mass}[args.workload](args)
+        res = {"small": run_small, "batched": run_batched, "mass": run_mass,
+               "precision": run_precision}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     import numpy as np
@@ -403,6 +545,12 @@ def main():
         roof["achieved"] = per_unit * traj_rate / 1e12
         roof["frac"] = roof["achieved"] / peak
         roof["flop_per_site_update"] = per_unit
+    tr = measured_traffic(args.precision, S, NW, T, k)
+    if tr:
+        roof["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
+        roof["traffic_detail"] = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
+                                  "per": "k_traj launch (one trajectory)",
+                                  "algorithmic_bytes": 40.0 * T if args.precision == "f64" else 20.0 * T}
     stream_gbs = STREAM_BYTES[args.precision] * traj_rate / 1e9
 
     res = {

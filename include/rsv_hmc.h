@@ -66,6 +66,13 @@ typedef enum { RSV_F64 = 0, RSV_F32_MIXED = 1 } rsv_precision;
  * updated. */
 enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
 
+/* Execution flags.  By default rsv_hmc_sweep runs every sweep of a call in a
+ * single launch when each chain fits one tile of four wavefronts (the chain
+ * stays resident in one block: trajectory, dH, Metropolis and theta update
+ * separated by block barriers); RSV_FLAG_NO_RESIDENT forces one launch per
+ * kernel per sweep instead.  Results are identical either way. */
+enum { RSV_FLAG_NO_RESIDENT = 1 };
+
 /* theta of Sec. 2. */
 typedef struct { double phi, mu, xi, sig2_eta, sig2_u; } rsv_theta;
 
@@ -93,11 +100,14 @@ typedef struct {
     int32_t sites_per_lane;     /* tile shape of the trajectory kernel: sites
                                    held by each lane (0 = library default;
                                    RSV_F64: 4 or 8, RSV_F32_MIXED: 8 or 16)    */
-    int32_t waves_per_tile;     /* wavefronts per tile (0 = default; 1 or 4).
+    int32_t waves_per_tile;     /* wavefronts per tile (0 = default 4; compiled
+                                   (S, NW): F64 (4,1) (4,4) (8,1) (8,2) (8,4)
+                                   (8,8); F32 (8,1) (8,4) (8,8) (16,1) (16,2)
+                                   (16,4)).
                                    A tile spans 64 * waves_per_tile *
                                    sites_per_lane sites, of which all but a
                                    k+1 halo on each cut side are exact          */
-    int32_t reserved;
+    int32_t flags;              /* RSV_FLAG_* bit set (0 = defaults)           */
     uint64_t seed;              /* key of all random streams                   */
     rsv_prior prior;
 } rsv_problem;

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "librsvhmc.so")
 RSV_OK, RSV_EINVAL, RSV_EDEVICE, RSV_ENOMEM, RSV_ESTATE, RSV_ENONFINITE = 0, -1, -2, -3, -4, -5
 RSV_F64, RSV_F32_MIXED = 0, 1
 RSV_TERM_RETURN, RSV_TERM_RV, RSV_TERMS_RSV = 1, 2, 3
+RSV_FLAG_NO_RESIDENT = 1
 
 THETA_KEYS = ("phi", "mu", "xi", "sig2_eta", "sig2_u")
 PRIOR_KEYS = ("mu_mean", "mu_var", "xi_mean", "xi_var",
@@ -52,7 +53,7 @@ class rsv_problem(C.Structure):
         ("max_steps", C.c_int32),
         ("sites_per_lane", C.c_int32),
         ("waves_per_tile", C.c_int32),
-        ("reserved", C.c_int32),
+        ("flags", C.c_int32),
         ("seed", C.c_uint64),
         ("prior", rsv_prior),
     ]

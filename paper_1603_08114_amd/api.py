@@ -67,6 +67,7 @@ class Problem:
     max_steps: int = 50
     sites_per_lane: int = 0
     waves_per_tile: int = 0
+    flags: int = 0
     seed: int = 0
     prior: dict = field(default_factory=lambda: dict(DEFAULT_PRIOR))
 
@@ -93,6 +94,7 @@ class Problem:
         pb.max_steps = int(self.max_steps)
         pb.sites_per_lane = int(self.sites_per_lane)
         pb.waves_per_tile = int(self.waves_per_tile)
+        pb.flags = int(self.flags)
         pb.seed = int(self.seed)
         pr = dict(DEFAULT_PRIOR)
         pr.update(self.prior or {})
@@ -198,7 +200,7 @@ class RSVSampler:
 
     def __init__(self, offsets, y, log_rv, h0, theta0, chains_per_series=1,
                  precision=L.RSV_F64, terms=L.RSV_TERMS_RSV, max_steps=50, seed=0,
-                 prior=None, log_mass=None, sites_per_lane=0, waves_per_tile=0,
+                 prior=None, log_mass=None, sites_per_lane=0, waves_per_tile=0, flags=0,
                  device="cuda"):
         if not torch.cuda.is_available():
             raise RuntimeError("RSVSampler needs a GPU (HIP device)")
@@ -209,7 +211,7 @@ class RSVSampler:
         self.pb = Problem(offsets=np.asarray(offsets, np.int64), y=self.y, log_rv=self.log_rv,
                           chains_per_series=chains_per_series, precision=precision, terms=terms,
                           max_steps=max_steps, sites_per_lane=sites_per_lane,
-                          waves_per_tile=waves_per_tile, seed=seed,
+                          waves_per_tile=waves_per_tile, flags=flags, seed=seed,
                           prior=prior or dict(DEFAULT_PRIOR))
         state_dtype = torch.float64 if precision == L.RSV_F64 else torch.float32
         self.n_state = rsv_hmc_state_size(self.pb)

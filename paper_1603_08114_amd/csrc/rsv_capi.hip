@@ -203,6 +203,7 @@ struct rsv_ctx {
     std::vector<ChainDesc> h_chains;
     int32_t n_body = 0, n_edge = 0;
     int32_t max_tiles_per_chain = 0;
+    bool single_tile = false;  // every chain is one tile
     // kernel timing: event pairs around each trajectory-kernel launch
     std::vector<hipEvent_t> ev_start, ev_stop;
     size_t ev_used = 0;
@@ -255,8 +256,11 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
         chains[ch].tile_begin += n_edge;
     }
     c->max_tiles_per_chain = 0;
-    for (const ChainDesc& d : chains)
+    c->single_tile = true;
+    for (const ChainDesc& d : chains) {
         c->max_tiles_per_chain = std::max(c->max_tiles_per_chain, d.tile_count + 1);
+        c->single_tile = c->single_tile && (d.tile_count + (d.edge_tile >= 0 ? 1 : 0) == 1);
+    }
     c->n_body = static_cast<int32_t>(body.size());
     c->n_edge = static_cast<int32_t>(edges.size());
     c->h_tiles = edges;
@@ -322,12 +326,7 @@ rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0) {
     return RSV_OK;
 }
 
-rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
-                          double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
-                          void* h_trace, double* stats_out) {
-    const rsv_status st = c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0)
-                                                     : launch_traj_all<float>(c, sweep, p0);
-    if (st != RSV_OK) return st;
+FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do_theta) {
     FinalizeArgs f;
     f.chains = c->chains;
     f.n_chains = c->n_chains;
@@ -338,19 +337,54 @@ rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const do
     f.seed = c->pb.seed;
     f.sweep = sweep;
     f.terms = c->pb.terms;
-    f.do_metropolis = 1;
+    f.do_metropolis = do_metropolis;
     f.do_theta = do_theta;
-    f.log_u = log_u;
+    f.log_u = nullptr;
     f.state_sel = c->accept;
+    f.delta_h_out = nullptr;
+    f.accepted_out = nullptr;
+    f.theta_trace = nullptr;
+    f.stats_out = nullptr;
+    f.counters = c->counters;
+    return f;
+}
+
+rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
+                          double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
+                          void* h_trace, double* stats_out) {
+    const rsv_status st = c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0)
+                                                     : launch_traj_all<float>(c, sweep, p0);
+    if (st != RSV_OK) return st;
+    FinalizeArgs f = finalize_args(c, sweep, 1, do_theta);
+    f.log_u = log_u;
     f.delta_h_out = delta_h;
     f.accepted_out = accepted;
     f.theta_trace = theta_trace;
     f.stats_out = stats_out;
-    f.counters = c->counters;
     RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
     if (h_trace)
         RSV_HIP(launch_gather_state(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
                                     c->h_prop, h_trace, c->pb.precision));
+    return RSV_OK;
+}
+
+template <typename R>
+rsv_status run_resident(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps, int update_theta,
+                        const rsv_trace* trace) {
+    ResidentArgs<R> ra;
+    ra.traj = traj_args<R>(c, first_sweep, nullptr);
+    ra.fin = finalize_args(c, first_sweep, 1, update_theta);
+    ra.n_sweeps = n_sweeps;
+    ra.batch_len = (trace && trace->h_batch_sum) ? trace->batch_len : 1;
+    ra.first_sweep = first_sweep;
+    ra.n_state = c->n_state;
+    ra.dh_trace = trace ? trace->delta_h : nullptr;
+    ra.acc_trace = trace ? trace->accepted : nullptr;
+    ra.theta_trace = trace ? trace->theta : nullptr;
+    ra.h_trace = trace ? static_cast<R*>(trace->h) : nullptr;
+    ra.batch_sum = trace ? trace->h_batch_sum : nullptr;
+    ra.sq_sum = trace ? trace->h_sq_sum : nullptr;
+    RSV_HIP(launch_resident(c->stream, c->pb.precision, c->S, c->log_mass != nullptr, &ra));
     return RSV_OK;
 }
 
@@ -492,25 +526,8 @@ rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
     RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
                          c->h_prop, c->accept, c->pb.log_rv, c->partials, c->edge,
                          c->pb.precision));
-    FinalizeArgs f;
-    f.chains = c->chains;
-    f.n_chains = c->n_chains;
-    f.partials = c->partials;
-    f.chain_edge = c->edge;
-    f.theta = c->theta;
-    f.prior = c->pb.prior;
-    f.seed = c->pb.seed;
-    f.sweep = sweep;
-    f.terms = c->pb.terms;
-    f.do_metropolis = 0;
-    f.do_theta = 1;
-    f.log_u = nullptr;
-    f.state_sel = c->accept;
-    f.delta_h_out = nullptr;
-    f.accepted_out = nullptr;
-    f.theta_trace = nullptr;
+    FinalizeArgs f = finalize_args(c, sweep, 0, 1);
     f.stats_out = suff_stats;
-    f.counters = c->counters;
     RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
     return RSV_OK;
 }
@@ -523,6 +540,14 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         return fail(RSV_EINVAL, "batch_len must be >= 1 with h_batch_sum");
     rsv_status st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
+    const bool timing = c->ev_used < c->ev_start.size();
+    if (n_sweeps > 0 && c->single_tile && c->NW == 4 && !timing &&
+        !(c->pb.flags & RSV_FLAG_NO_RESIDENT)) {
+        st = c->pb.precision == RSV_F64
+                 ? run_resident<double>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace)
+                 : run_resident<float>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace);
+        return st != RSV_OK ? st : settle(c);
+    }
     const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
     for (int32_t i = 0; i < n_sweeps; ++i) {
         const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;

@@ -93,6 +93,22 @@ struct FinalizeArgs {
 // Record the message returned by rsv_last_error() and return `code`.
 rsv_status set_error(rsv_status code, const char* where, const char* what);
 
+template <typename R>
+struct ResidentArgs {
+    TrajArgs<R> traj;          // sweep field ignored (first_sweep + i)
+    FinalizeArgs fin;          // sweep and per-sweep outputs ignored (set per sweep)
+    int32_t n_sweeps;
+    int32_t batch_len;
+    uint64_t first_sweep;
+    int64_t n_state;
+    double* dh_trace;          // n_sweeps * n_chains or nullptr
+    int32_t* acc_trace;
+    rsv_theta* theta_trace;
+    R* h_trace;                // n_sweeps * n_state or nullptr
+    double* batch_sum;         // accumulators (see rsv_trace) or nullptr
+    double* sq_sum;
+};
+
 // Launchers (rsv_kernels.hip).  Each returns the hipError_t of its launch.
 hipError_t launch_prepare(hipStream_t st, const double* y, const double* lrv, int64_t n,
                           double* y2_d, float* y2_f, float* lrv_f);
@@ -103,6 +119,8 @@ hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
 bool traj_shape_available(int precision, int S, int NW);
 void traj_default_shape(int precision, int* S, int* NW);
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain);
+// All n sweeps of chains that each fit one tile of four wavefronts, in one launch.
+hipError_t launch_resident(hipStream_t st, int precision, int S, bool mass, const void* args);
 // Copy every chain's current state (selected by state_sel) into h_dst.
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,

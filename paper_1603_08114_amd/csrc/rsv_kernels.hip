@@ -259,15 +259,16 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             for (int q = 0; q < 11; ++q) sh.red[wv][q] = red[q];
         }
         __syncthreads();
-        if (wv != 0) return;
+        if (wv == 0) {
 #pragma unroll
-        for (int q = 0; q < 11; ++q) {
-            double v = sh.red[0][q];
-            for (int x = 1; x < NW; ++x) v += sh.red[x][q];
-            red[q] = v;
+            for (int q = 0; q < 11; ++q) {
+                double v = sh.red[0][q];
+                for (int x = 1; x < NW; ++x) v += sh.red[x][q];
+                red[q] = v;
+            }
         }
     }
-    if (lane == 0) {
+    if (wv == 0 && lane == 0) {
         double* out = A.partials + static_cast<int64_t>(tile_id) * kPart;
 #pragma unroll
         for (int q = 0; q < 11; ++q) out[q] = red[q];
@@ -277,10 +278,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 // One launch covers every tile; tiles whose chain ends inside a lane (EDGE)
 // take the variant that substitutes the end-point neighbour per site.
 template <typename R, int S, int NW, bool MASS, bool RET>
-__global__ __launch_bounds__(256) void k_traj(TrajArgs<R> A) {
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void k_traj(TrajArgs<R> A) {
     static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
-    static_assert(NW == 1 || NW == 4, "one tile per wavefront or per 256-thread block");
-    constexpr int kTilesPerBlock = 4 / NW;
+    static_assert(NW == 1 || NW == 2 || NW == 4 || NW == 8, "tile shapes");
+    // NW = 1: four independent tiles per 256-thread block (no barriers);
+    // NW > 1: one tile per block of NW wavefronts, so a barrier never spans
+    // tiles of chains with different k.
+    constexpr int kTilesPerBlock = NW == 1 ? 4 : 1;
     __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv_blk = threadIdx.x / kWave;
@@ -442,13 +446,15 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
 // Per-chain finalize: reduce tile partials (compensated, fixed order), the
 // Metropolis test, the choice of statistics, and the theta update.
 // ---------------------------------------------------------------------------
+constexpr int kNQ = 11;
+
+// Everything the finalize does for chain c, by the NT threads of a block
+// (shared scratch passed in); returns in every thread.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
+__device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[NT / kWave][kNQ],
+                               ThetaDraws& draws) {
     constexpr int NW = NT / kWave;
-    constexpr int NQ = 11;
-    __shared__ Comp part[NW][NQ];
-    __shared__ ThetaDraws draws;
-    const int c = blockIdx.x;
+    constexpr int NQ = kNQ;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
@@ -525,6 +531,66 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
         A.theta[c] = out;
     }
     if (A.theta_trace) A.theta_trace[c] = out;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
+    __shared__ Comp part[NT / kWave][kNQ];
+    __shared__ ThetaDraws draws;
+    finalize_chain<NT>(A, blockIdx.x, part, draws);
+}
+
+// ---------------------------------------------------------------------------
+// Resident sweeps: chains that fit one tile of four wavefronts run all n
+// sweeps (trajectory, dH, Metropolis, theta update, traces) in one launch,
+// one block per chain; the phases are separated by block barriers.
+// ---------------------------------------------------------------------------
+template <typename R, int S, bool MASS, bool RET>
+__global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
+    __shared__ TileShared<R, 4> sh;
+    __shared__ Comp part[4][kNQ];
+    __shared__ ThetaDraws draws;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const ChainDesc cd = RA.traj.chains[c];
+    const bool edge = cd.edge_tile >= 0;
+    const int tile_id = edge ? cd.edge_tile : cd.tile_begin;
+    const int n_chains = RA.fin.n_chains;
+    for (int i = 0; i < RA.n_sweeps; ++i) {
+        TrajArgs<R> A = RA.traj;
+        A.sweep = RA.first_sweep + static_cast<uint64_t>(i);
+        if (edge)
+            traj_tile<R, S, 4, MASS, true, RET>(A, sh, tile_id, wv, lane);
+        else
+            traj_tile<R, S, 4, MASS, false, RET>(A, sh, tile_id, wv, lane);
+        __syncthreads();
+        FinalizeArgs F = RA.fin;
+        F.sweep = A.sweep;
+        const int64_t ofs = static_cast<int64_t>(i) * n_chains;
+        F.delta_h_out = RA.dh_trace ? RA.dh_trace + ofs : nullptr;
+        F.accepted_out = RA.acc_trace ? RA.acc_trace + ofs : nullptr;
+        F.theta_trace = RA.theta_trace ? RA.theta_trace + ofs : nullptr;
+        finalize_chain<256>(F, c, part, draws);
+        __syncthreads();
+        if (RA.h_trace || RA.batch_sum || RA.sq_sum) {
+            const R* src = (RA.traj.state_sel[c] ? RA.traj.h_b : RA.traj.h_a) + cd.h_off;
+            R* ht = RA.h_trace ? RA.h_trace + static_cast<int64_t>(i) * RA.n_state + cd.h_off
+                               : nullptr;
+            double* bs = RA.batch_sum
+                             ? RA.batch_sum + static_cast<int64_t>(i / RA.batch_len) * RA.n_state + cd.h_off
+                             : nullptr;
+            double* sq = RA.sq_sum ? RA.sq_sum + cd.h_off : nullptr;
+            for (int t = threadIdx.x; t < cd.T; t += blockDim.x) {
+                const R v = src[t];
+                if (ht) ht[t] = v;
+                const double vd = static_cast<double>(v);
+                if (bs) bs[t] += vd;
+                if (sq) sq[t] += vd * vd;
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -633,8 +699,8 @@ inline int grid_for(int64_t n, int block, int cap) {
 template <typename R, int S, int NW>
 hipError_t launch_traj_t(hipStream_t st, bool mass, bool ret, const TrajArgs<R>& a) {
     if (a.n_list <= 0) return hipSuccess;
-    constexpr int per_block = 4 / NW;
-    const dim3 grid((a.n_list + per_block - 1) / per_block), block(256);
+    constexpr int per_block = NW == 1 ? 4 : 1;
+    const dim3 grid((a.n_list + per_block - 1) / per_block), block(NW == 1 ? 256 : 64 * NW);
 #define RSV_TRAJ(M, RT) hipLaunchKernelGGL((k_traj<R, S, NW, M, RT>), grid, block, 0, st, a)
     if (ret) { if (mass) RSV_TRAJ(true, true); else RSV_TRAJ(false, true); }
     else     { if (mass) RSV_TRAJ(true, false); else RSV_TRAJ(false, false); }
@@ -647,8 +713,9 @@ hipError_t launch_traj_t(hipStream_t st, bool mass, bool ret, const TrajArgs<R>&
 // Tile shapes compiled for each precision: (sites per lane, wavefronts per
 // tile); the first is the default.
 bool traj_shape_available(int precision, int S, int NW) {
-    if (NW != 1 && NW != 4) return false;
-    return precision == RSV_F64 ? (S == 4 || S == 8) : (S == 8 || S == 16);
+    if (precision == RSV_F64)
+        return (S == 4 && (NW == 1 || NW == 4)) || (S == 8 && (NW == 1 || NW == 2 || NW == 4 || NW == 8));
+    return (S == 8 && (NW == 1 || NW == 4 || NW == 8)) || (S == 16 && (NW == 1 || NW == 2 || NW == 4));
 }
 void traj_default_shape(int precision, int* S, int* NW) {
     *S = 8;
@@ -664,13 +731,17 @@ hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
         if (S == 4 && NW == 1) return launch_traj_t<double, 4, 1>(st, mass, ret, a);
         if (S == 4 && NW == 4) return launch_traj_t<double, 4, 4>(st, mass, ret, a);
         if (S == 8 && NW == 1) return launch_traj_t<double, 8, 1>(st, mass, ret, a);
+        if (S == 8 && NW == 2) return launch_traj_t<double, 8, 2>(st, mass, ret, a);
         if (S == 8 && NW == 4) return launch_traj_t<double, 8, 4>(st, mass, ret, a);
+        if (S == 8 && NW == 8) return launch_traj_t<double, 8, 8>(st, mass, ret, a);
     } else {
         const auto& a = *static_cast<const TrajArgs<float>*>(args);
         const bool ret = (a.terms & RSV_TERM_RETURN) != 0;
         if (S == 8 && NW == 1) return launch_traj_t<float, 8, 1>(st, mass, ret, a);
         if (S == 8 && NW == 4) return launch_traj_t<float, 8, 4>(st, mass, ret, a);
+        if (S == 8 && NW == 8) return launch_traj_t<float, 8, 8>(st, mass, ret, a);
         if (S == 16 && NW == 1) return launch_traj_t<float, 16, 1>(st, mass, ret, a);
+        if (S == 16 && NW == 2) return launch_traj_t<float, 16, 2>(st, mass, ret, a);
         if (S == 16 && NW == 4) return launch_traj_t<float, 16, 4>(st, mass, ret, a);
     }
     return hipErrorInvalidValue;
@@ -705,6 +776,34 @@ hipError_t launch_validate(hipStream_t st, const double* y, const double* lrv, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_count_nonfinite(st, h, n_state, precision, counters + kCntNonfiniteState);
+}
+
+template <typename R, int S>
+hipError_t launch_resident_t(hipStream_t st, bool mass, bool ret, const ResidentArgs<R>& a) {
+    const dim3 grid(a.fin.n_chains), block(256);
+    if (ret) {
+        if (mass) hipLaunchKernelGGL((k_resident<R, S, true, true>), grid, block, 0, st, a);
+        else      hipLaunchKernelGGL((k_resident<R, S, false, true>), grid, block, 0, st, a);
+    } else {
+        if (mass) hipLaunchKernelGGL((k_resident<R, S, true, false>), grid, block, 0, st, a);
+        else      hipLaunchKernelGGL((k_resident<R, S, false, false>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(hipStream_t st, int precision, int S, bool mass, const void* args) {
+    if (precision == RSV_F64) {
+        const auto& a = *static_cast<const ResidentArgs<double>*>(args);
+        const bool ret = (a.traj.terms & RSV_TERM_RETURN) != 0;
+        if (S == 4) return launch_resident_t<double, 4>(st, mass, ret, a);
+        if (S == 8) return launch_resident_t<double, 8>(st, mass, ret, a);
+    } else {
+        const auto& a = *static_cast<const ResidentArgs<float>*>(args);
+        const bool ret = (a.traj.terms & RSV_TERM_RETURN) != 0;
+        if (S == 8) return launch_resident_t<float, 8>(st, mass, ret, a);
+        if (S == 16) return launch_resident_t<float, 16>(st, mass, ret, a);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain) {

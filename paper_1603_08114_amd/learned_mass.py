@@ -30,11 +30,12 @@ def _series_view(off, C):
     return Ts, np.concatenate([[0], np.cumsum(Ts * C)])
 
 
-def adapt(smp, lf_k, dtau, sweep, windows, n_series, C, win=50, target=0.8, gain=1.5):
+def adapt(smp, lf_k, dtau, sweep, windows, n_series, C, win=50, target=0.8, gain=1.5,
+          update_theta=True):
     """Per-series dtau: after each window of `win` sweeps,
     dtau *= exp(gain (mean min(1, e^-dH) - target))."""
     for _ in range(windows):
-        out = smp.sweep(sweep, win, [(lf_k, d) for d in dtau], update_theta=True,
+        out = smp.sweep(sweep, win, [(lf_k, d) for d in dtau], update_theta=update_theta,
                         record=("delta_h", "theta"))
         sweep += win
         dh = out["delta_h"].cpu().numpy().reshape(win, n_series, C)
@@ -44,14 +45,15 @@ def adapt(smp, lf_k, dtau, sweep, windows, n_series, C, win=50, target=0.8, gain
     return dtau, sweep, acc, last_theta
 
 
-def measure(smp, lf_k, dtau, sweep, n, bl, off, C):
+def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
     """n measured sweeps; returns per-series min-ESS (h part, theta part),
-    elapsed seconds, acceptance, and pooled per-data-site mean/var of h."""
+    elapsed seconds, acceptance, and pooled per-data-site mean/var of h.
+    With theta held fixed only the h part is meaningful (ess_theta is inf)."""
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(smp.stream)
-    out = smp.sweep(sweep, n, [(lf_k, d) for d in dtau], update_theta=True,
+    out = smp.sweep(sweep, n, [(lf_k, d) for d in dtau], update_theta=update_theta,
                     record=("theta", "accepted"), batch_len=bl)
     ev1.record(smp.stream)
     torch.cuda.synchronize()
@@ -79,8 +81,11 @@ def measure(smp, lf_k, dtau, sweep, n, bl, off, C):
         pm = m_c.mean(0)
         pooled_mean[off[s]:off[s + 1]] = pm
         pooled_var[off[s]:off[s + 1]] = (v_c + m_c * m_c).mean(0) - pm * pm
-        e_th = sum(diagnostics.ess_geyer(th[:, s * C + j, :]) for j in range(C))
-        ess_th[s] = float(np.min(e_th))
+        if update_theta:
+            e_th = sum(diagnostics.ess_geyer(th[:, s * C + j, :]) for j in range(C))
+            ess_th[s] = float(np.min(e_th))
+        else:
+            ess_th[s] = np.inf
     # MCSE^2 of the pooled (over chains) posterior mean of each data site
     pooled_mcse2 = torch.empty_like(pooled_mean)
     mc2 = var / ess
@@ -103,8 +108,11 @@ def chains_for(data, C):
     return h0, thetas
 
 
-def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25):
-    """One arm on one batch of series; returns measure() output plus dtau."""
+def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True):
+    """One arm on one batch of series; returns measure() output plus dtau.
+    update_theta=False holds every chain at its series' generating theta (an
+    exactness check of the h update alone: the h-conditional mixes in a few
+    sweeps, so batch-means standard errors are reliable)."""
     off = data["offsets"]
     S = len(off) - 1
     Ts = np.diff(off)
@@ -112,7 +120,8 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25):
     kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed)
     smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, **kw)
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
-    dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 100, S, C)
+    dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 100, S, C,
+                                      update_theta=update_theta)
     log_m = None
     if net is not None:
         theta_hat = theta_now.mean(axis=0).reshape(S, C, 5).mean(axis=1)
@@ -123,8 +132,8 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25):
         smp.close()
         smp = api.RSVSampler(off, data["y"], data["log_rv"], state, th_now,
                              log_mass=log_m.cpu().numpy(), **kw)
-    dtau, sweep, _, _ = adapt(smp, k, dtau, sweep, warm // 100, S, C)
-    res = measure(smp, k, dtau, sweep, n, bl, off, C)
+    dtau, sweep, _, _ = adapt(smp, k, dtau, sweep, warm // 100, S, C, update_theta=update_theta)
+    res = measure(smp, k, dtau, sweep, n, bl, off, C, update_theta=update_theta)
     res["dtau"] = dtau
     res["log_mass"] = None if log_m is None else log_m
     smp.close()

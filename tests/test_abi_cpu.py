@@ -66,7 +66,7 @@ def test_workspace_and_state_sizes():
     dict(offsets=[0, 100], sites_per_lane=5),
     dict(offsets=[0, 100], chains_per_series=0),
     dict(offsets=[0, 5000], max_steps=400, sites_per_lane=8, waves_per_tile=1),  # halo > tile
-    dict(offsets=[0, 100], waves_per_tile=2),
+    dict(offsets=[0, 100], waves_per_tile=3),
     dict(offsets=[0, 100], prior=dict(mu_var=-1.0)),
 ])
 def test_invalid_problems_rejected_on_host(bad):

@@ -76,7 +76,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("Ts,C,k,dt", SHAPES)
-@pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 4), (8, 4)])
+@pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 4), (8, 2), (8, 4), (8, 8)])
 def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
     smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW)
     rng = np.random.default_rng(3)
@@ -292,3 +292,57 @@ def test_batch_mean_accumulators_match_recorded_trace():
         sq += h[i] * h[i]
     # the device forms v*v + sum with one FMA rounding
     np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq, rtol=1e-14)
+
+
+@pytest.mark.parametrize("precision", [RSV_F64, RSV_F32_MIXED])
+def test_resident_sweeps_equal_per_kernel_sweeps(precision):
+    """Chains that fit one tile run all sweeps in one launch; the result must
+    be bitwise the one of one launch per kernel per sweep."""
+    from paper_1603_08114_amd._lib import RSV_FLAG_NO_RESIDENT
+    Ts, C, k, dt, n = [1000, 37, 2048, 1501], 3, 20, 0.04, 40
+    thetas = synth.draw_batch_thetas(len(Ts), 9)
+    offsets, ys, rs, hs = make_series(Ts, 300, thetas)
+    h0 = state_from(hs, C, 0.02)
+    th = [thetas[s] for s in range(len(Ts)) for _ in range(C)]
+    outs = []
+    for flags in (0, RSV_FLAG_NO_RESIDENT):
+        smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
+                             chains_per_series=C, precision=precision, max_steps=k, seed=4,
+                             flags=flags)
+        o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True, batch_len=7)
+        o["state"] = smp.h.clone()
+        o["theta_final"] = smp.theta.clone()
+        outs.append(o)
+    for key in ("delta_h", "accepted", "theta", "h", "h_batch_sum", "h_sq_sum", "state",
+                "theta_final"):
+        assert torch.equal(outs[0][key], outs[1][key]), key
+    assert outs[0]["accepted"].float().mean() > 0.3
+
+
+def test_autotuner_picks_a_compiled_shape_and_caches(tmp_path):
+    from paper_1603_08114_amd import autotune
+    offsets, ys, rs, hs = make_series([3000, 700], 21)
+    th = [TH, TH]
+    cache = str(tmp_path / "shapes.json")
+    S, NW, table = autotune.best_shape(offsets, np.concatenate(ys), np.concatenate(rs),
+                                       np.concatenate(hs), th, (30, 0.04), cache_path=cache,
+                                       n_sweeps=3)
+    assert (S, NW) in autotune.SHAPES[RSV_F64] and len(table) == len(autotune.SHAPES[RSV_F64])
+    assert min(table.values()) == table[f"{S},{NW}"]
+    S2, NW2, _ = autotune.best_shape(offsets, np.concatenate(ys), np.concatenate(rs),
+                                     np.concatenate(hs), th, (30, 0.04), cache_path=cache)
+    assert (S2, NW2) == (S, NW)
+
+
+def test_tile_shapes_give_the_same_trajectory():
+    """The per-site arithmetic does not depend on the tiling: h after a
+    trajectory is bitwise equal across tile shapes."""
+    k, dt = 30, 0.03
+    outs = []
+    for S, NW in [(4, 1), (8, 1), (4, 4), (8, 2), (8, 4), (8, 8)]:
+        smp, offsets, ys, rs, h0, th = sampler([5000, 1200], 2, k=k, S=S, NW=NW)
+        p0 = np.random.default_rng(2).standard_normal(h0.size)
+        smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
+        outs.append(smp.h.cpu().numpy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
