@@ -109,6 +109,14 @@ typedef struct {
                                    k+1 halo on each cut side are exact          */
     int32_t flags;              /* RSV_FLAG_* bit set (0 = defaults)           */
     uint64_t seed;              /* key of all random streams                   */
+    double dtau_jitter;         /* j in [0, 1): the step size of every
+                                   trajectory is dtau * (1 + j (2u - 1)), u the
+                                   first uniform of Philox block (0, sweep,
+                                   chain, tag 3); 0 = the paper's fixed dtau.
+                                   An extension: a factor drawn independently
+                                   of the state keeps the chain exact and
+                                   breaks near-periodic orbits of modes whose
+                                   period divides k * dtau                      */
     rsv_prior prior;
 } rsv_problem;
 

@@ -71,8 +71,9 @@ def _load():
         "orc_gamma": (C.c_double, [C.c_double, _U64, _U64, _U64, _U64, _U64,
                                    P(C.c_int)]),
         "orc_neumaier_sum": (C.c_double, [_I64, _D]),
+        "orc_step_size": (C.c_double, [_U64, _U64, _U64, C.c_double, C.c_double]),
         "orc_run": (_I64, [_I64, _D, P(Theta), _D, _D, _D, P(Prior), C.c_int, C.c_int32,
-                           C.c_double, _U64, _U64, _U64, _I64, C.c_int, _D,
+                           C.c_double, C.c_double, _U64, _U64, _U64, _I64, C.c_int, _D,
                            P(C.c_int32), P(Theta), _D]),
     }
     for name, (res, args) in sig.items():
@@ -189,9 +190,15 @@ def log_u(seed, sweep, chain):
     return _lib.orc_log_u(seed, sweep, chain)
 
 
+def step_size(seed, sweep, chain, dtau, jitter):
+    """dtau of (seed, sweep, chain) under step-size jitter (jitter 0: dtau)."""
+    return _lib.orc_step_size(seed, sweep, chain, float(dtau), float(jitter))
+
+
 def trajectory(h, y2, r, theta, k, dtau, seed=0, sweep=0, chain=0, terms=TERMS_RSV,
-               p0=None, log_u=None, log_m=None):
+               p0=None, log_u=None, log_m=None, jitter=0.0):
     """One HMC trajectory.  Returns dict(h, accepted, dH, p0)."""
+    dtau = step_size(seed, sweep, chain, dtau, jitter)
     h = _arr(h).copy(); T = h.size
     lm = None if log_m is None else _arr(log_m, T)
     p0a = None if p0 is None else _arr(p0, T)
@@ -243,7 +250,7 @@ def neumaier_sum(x):
 
 
 def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
-        update_theta=True, prior=None, terms=TERMS_RSV, log_m=None, keep_h=False):
+        update_theta=True, prior=None, terms=TERMS_RSV, log_m=None, keep_h=False, jitter=0.0):
     """n sweeps of one chain.  Returns dict with final h/theta and traces."""
     h = _arr(h).copy(); T = h.size
     th = theta_struct(theta)
@@ -255,7 +262,8 @@ def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
     htrace = np.zeros((n_sweeps, T)) if keep_h else None
     n_acc = _lib.orc_run(T, _ptr(h), C.byref(th), _ptr(lm), _ptr(_arr(y2, T)),
                          _ptr(_arr(r, T)), C.byref(prior_struct(prior)), terms, int(k),
-                         float(dtau), seed, chain, first_sweep, n_sweeps, int(update_theta),
+                         float(dtau), float(jitter), seed, chain, first_sweep, n_sweeps,
+                         int(update_theta),
                          _ptr(dH), acc.ctypes.data_as(C.POINTER(C.c_int32)), ttrace,
                          _ptr(htrace))
     theta_tr = np.array([[getattr(ttrace[i], k_) for k_ in THETA_KEYS]

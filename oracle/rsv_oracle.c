@@ -258,6 +258,21 @@ double orc_log_u(uint64_t seed, uint64_t sweep, uint64_t chain)
     return log(u[0]);
 }
 
+/* Step-size jitter (an extension of the fixed dtau of Sec. 2): the length
+ * k * dtau of every trajectory is scaled by a factor uniform on [1-j, 1+j],
+ * drawn independently of the state, which keeps the Markov chain exact and
+ * breaks the near-periodic orbits of modes whose period divides k * dtau. */
+double orc_step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau, double jitter)
+{
+    if (!(jitter > 0.0)) return dtau;
+    double u[4];
+    orc_uniforms4(seed, 0, sweep, chain, ORC_TAG_STEP, u);
+    double w = 2.0 * u[0] - 1.0;
+    double f = jitter * w;
+    f = 1.0 + f;
+    return dtau * f;
+}
+
 int orc_trajectory(int64_t T, double *h, const double *log_m,
                    const double *y2, const double *r, const orc_theta *th, int terms,
                    int32_t k, double dtau, uint64_t seed, uint64_t sweep, uint64_t chain,
@@ -426,7 +441,7 @@ int orc_theta_update(int64_t T, const double st[7], const orc_theta *th_in,
 
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, uint64_t seed, uint64_t chain,
+                int32_t k, double dtau, double jitter, uint64_t seed, uint64_t chain,
                 uint64_t first_sweep, int64_t n_sweeps, int update_theta,
                 double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
                 double *h_trace)
@@ -435,7 +450,8 @@ int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
     for (int64_t i = 0; i < n_sweeps; ++i) {
         uint64_t sweep = first_sweep + (uint64_t)i;
         double dH;
-        int acc = orc_trajectory(T, h, log_m, y2, r, th, terms, k, dtau, seed, sweep, chain,
+        double dt = orc_step_size(seed, sweep, chain, dtau, jitter);
+        int acc = orc_trajectory(T, h, log_m, y2, r, th, terms, k, dt, seed, sweep, chain,
                                  NULL, NULL, NULL, &dH);
         n_acc += acc;
         if (update_theta) {

@@ -43,7 +43,7 @@ typedef struct {
 enum { ORC_TERM_RETURN = 1, ORC_TERM_RV = 2, ORC_TERMS_RSV = 3 };
 
 /* Random-number stream tags (Philox counter word 3). */
-enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1, ORC_TAG_THETA = 2 };
+enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1, ORC_TAG_THETA = 2, ORC_TAG_STEP = 3 };
 
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
@@ -81,6 +81,11 @@ void orc_momenta(uint64_t seed, uint64_t sweep, uint64_t chain, int64_t T,
 /* log u of the Metropolis test of (seed, sweep, chain). */
 double orc_log_u(uint64_t seed, uint64_t sweep, uint64_t chain);
 
+/* Step size of sweep (seed, sweep, chain) under step-size jitter j in [0,1):
+ * dtau * (1 + j (2u - 1)) with u the first uniform of block 0 of stream tag 3
+ * (an extension: the paper's dtau is fixed; j = 0 returns dtau). */
+double orc_step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau, double jitter);
+
 /* One HMC trajectory on h (in place: left at h' if accepted, else at h0).
  * p0 / log_u may be NULL (then drawn from the streams).  p_out (may be NULL)
  * receives the momenta used.  Returns 1 if accepted, 0 if rejected. */
@@ -115,12 +120,13 @@ double orc_gamma(double alpha, uint64_t seed, uint64_t sweep, uint64_t chain, ui
 /* Compensated (Neumaier) sum. */
 double orc_neumaier_sum(int64_t n, const double *x);
 
-/* n sweeps (trajectory, then optional theta update) of one chain.
+/* n sweeps (trajectory, then optional theta update) of one chain; the step
+ * size of each sweep is orc_step_size(seed, sweep, chain, dtau, jitter).
  * Traces (each may be NULL): dH[n], acc[n], theta[n] (after the sweep),
  * h_trace[n*T] (h after each sweep).  Returns the number accepted. */
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, uint64_t seed, uint64_t chain,
+                int32_t k, double dtau, double jitter, uint64_t seed, uint64_t chain,
                 uint64_t first_sweep, int64_t n_sweeps, int update_theta,
                 double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
                 double *h_trace);

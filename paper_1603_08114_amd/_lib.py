@@ -55,6 +55,7 @@ class rsv_problem(C.Structure):
         ("waves_per_tile", C.c_int32),
         ("flags", C.c_int32),
         ("seed", C.c_uint64),
+        ("dtau_jitter", C.c_double),
         ("prior", rsv_prior),
     ]
 

@@ -69,6 +69,7 @@ class Problem:
     waves_per_tile: int = 0
     flags: int = 0
     seed: int = 0
+    dtau_jitter: float = 0.0
     prior: dict = field(default_factory=lambda: dict(DEFAULT_PRIOR))
 
     def __post_init__(self):
@@ -96,6 +97,7 @@ class Problem:
         pb.waves_per_tile = int(self.waves_per_tile)
         pb.flags = int(self.flags)
         pb.seed = int(self.seed)
+        pb.dtau_jitter = float(self.dtau_jitter)
         pr = dict(DEFAULT_PRIOR)
         pr.update(self.prior or {})
         pb.prior = L.rsv_prior(*[float(pr[k]) for k in L.PRIOR_KEYS])
@@ -201,7 +203,7 @@ class RSVSampler:
     def __init__(self, offsets, y, log_rv, h0, theta0, chains_per_series=1,
                  precision=L.RSV_F64, terms=L.RSV_TERMS_RSV, max_steps=50, seed=0,
                  prior=None, log_mass=None, sites_per_lane=0, waves_per_tile=0, flags=0,
-                 device="cuda"):
+                 dtau_jitter=0.0, device="cuda"):
         if not torch.cuda.is_available():
             raise RuntimeError("RSVSampler needs a GPU (HIP device)")
         self.device = torch.device(device)
@@ -212,7 +214,7 @@ class RSVSampler:
                           chains_per_series=chains_per_series, precision=precision, terms=terms,
                           max_steps=max_steps, sites_per_lane=sites_per_lane,
                           waves_per_tile=waves_per_tile, flags=flags, seed=seed,
-                          prior=prior or dict(DEFAULT_PRIOR))
+                          dtau_jitter=dtau_jitter, prior=prior or dict(DEFAULT_PRIOR))
         state_dtype = torch.float64 if precision == L.RSV_F64 else torch.float32
         self.n_state = rsv_hmc_state_size(self.pb)
         self.h = torch.as_tensor(np.asarray(h0, np.float64), **to).to(state_dtype).contiguous()

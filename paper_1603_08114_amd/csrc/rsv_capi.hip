@@ -111,6 +111,8 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     if (pb->terms < 1 || pb->terms > RSV_TERMS_RSV)
         return fail(RSV_EINVAL, "terms must be a non-empty subset of RSV_TERMS_RSV");
     if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
+    if (!(pb->dtau_jitter >= 0.0 && pb->dtau_jitter < 1.0))
+        return fail(RSV_EINVAL, "dtau_jitter must be in [0, 1)");
     const rsv_prior& p = pb->prior;
     if (!(p.mu_var > 0 && p.xi_var > 0 && p.eta_shape > 0 && p.eta_scale > 0 && p.u_shape > 0 &&
           p.u_scale > 0 && std::isfinite(p.mu_mean) && std::isfinite(p.xi_mean) &&
@@ -309,6 +311,7 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.sweep = sweep;
     a.partials = c->partials;
     a.chain_edge = c->edge;
+    a.jitter = c->pb.dtau_jitter;
     a.terms = c->pb.terms;
     return a;
 }

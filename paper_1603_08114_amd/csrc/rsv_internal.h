@@ -66,6 +66,7 @@ struct TrajArgs {
     uint64_t sweep;
     double* partials;           // kPart per tile
     double* chain_edge;         // kEdge per chain
+    double jitter;              // step-size jitter j (0: fixed dtau)
     int32_t terms;
 };
 

@@ -30,6 +30,21 @@ __device__ inline double exp_neg<double>(double x) { return exp_fast(-x); }
 template <>
 __device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
 
+// Step size of one trajectory: dtau scaled by 1 + j (2u - 1), u the first
+// uniform of block 0 of the step stream (every tile of a chain draws the same
+// u).  Rounded step by step, without contraction, so the value is exact to
+// the last bit for any caller that evaluates the same three operations.
+__device__ inline double step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau,
+                                   double jitter) {
+#pragma clang fp contract(off)
+    if (!(jitter > 0.0)) return dtau;
+    double u[4];
+    uniforms4(seed, 0, sweep, chain, kTagStep, u);
+    const double w = 2.0 * u[0] - 1.0;
+    const double f = 1.0 + jitter * w;
+    return dtau * f;
+}
+
 // ---------------------------------------------------------------------------
 // Trajectory kernel: momentum refresh, k leapfrog steps, per-site dH terms and
 // sufficient statistics of h' and h, for one tile per group of NW wavefronts.
@@ -59,7 +74,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const double phi = th.phi, mu = th.mu, xi = th.xi;
     const double inv_se = 1.0 / th.sig2_eta;
     const double inv_su = rv ? 1.0 / th.sig2_u : 0.0;
-    const double dt = cd.dtau;
+    const double dt = step_size(A.seed, A.sweep, static_cast<uint64_t>(td.chain), cd.dtau, A.jitter);
     // force g_t = c_t + alpha h_t - beta (h_{t-1} + h_{t+1}) - s_t e^{-h_t} / 2
     const double alpha = (1.0 + phi * phi) * inv_se + inv_su;
     const double beta = phi * inv_se;

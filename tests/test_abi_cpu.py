@@ -39,7 +39,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_lib.rsv_theta) == 40
     assert C.sizeof(_lib.rsv_prior) == 64
     assert C.sizeof(_lib.rsv_leapfrog) == 16
-    assert C.sizeof(_lib.rsv_problem) == 4 + 4 + 8 * 3 + 4 * 6 + 8 + 64
+    assert C.sizeof(_lib.rsv_problem) == 4 + 4 + 8 * 3 + 4 * 6 + 8 + 8 + 64
     assert C.sizeof(_lib.rsv_trace) == 56
 
 
@@ -67,6 +67,8 @@ def test_workspace_and_state_sizes():
     dict(offsets=[0, 100], chains_per_series=0),
     dict(offsets=[0, 5000], max_steps=400, sites_per_lane=8, waves_per_tile=1),  # halo > tile
     dict(offsets=[0, 100], waves_per_tile=3),
+    dict(offsets=[0, 100], dtau_jitter=1.0),
+    dict(offsets=[0, 100], dtau_jitter=-0.1),
     dict(offsets=[0, 100], prior=dict(mu_var=-1.0)),
 ])
 def test_invalid_problems_rejected_on_host(bad):

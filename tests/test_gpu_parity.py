@@ -42,13 +42,14 @@ def state_from(hs, C, jitter=0.0, seed=0):
 
 
 def sampler(Ts, C=1, seed=5, k=20, precision=RSV_F64, thetas=None, log_mass=None, S=0,
-            terms=3, jitter=0.05, NW=0):
+            terms=3, jitter=0.05, NW=0, dtau_jitter=0.0):
     offsets, ys, rs, hs = make_series(Ts, 100 + seed, thetas)
     h0 = state_from(hs, C, jitter)
     th = [thetas[s] if thetas else TH for s in range(len(Ts)) for _ in range(C)]
     smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                          chains_per_series=C, precision=precision, max_steps=k, seed=seed,
-                         log_mass=log_mass, sites_per_lane=S, waves_per_tile=NW, terms=terms)
+                         log_mass=log_mass, sites_per_lane=S, waves_per_tile=NW, terms=terms,
+                         dtau_jitter=dtau_jitter)
     return smp, offsets, ys, rs, h0, th
 
 
@@ -144,6 +145,82 @@ def test_trajectory_with_mass_f64():
         assert abs(dh[c] - ref["dH"]) <= 1e-9 * max(1.0, abs(ref["dH"]))
         assert bool(acc[c]) == ref["accepted"]
         assert rel_inf(h_gpu[sl], ref["h"]) <= 1e-12
+
+
+def test_trajectory_with_mass_multi_tile_chains_f64():
+    """Learned-mass scale (log m ~ 2.4 +- 0.7) on chains that span several
+    tiles, with several chains per series sharing the series' mass."""
+    Ts, C, k, dt = [5000, 1300], 2, 30, 0.08
+    lm = np.clip(2.4 + 0.7 * np.random.default_rng(4).standard_normal(sum(Ts)), -5, 5)
+    lm = lm.astype(np.float32)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, log_mass=lm)
+    dh, acc = smp.trajectory(6, (k, dt))
+    h_gpu, dh, acc = smp.h.cpu().numpy(), dh.cpu().numpy(), acc.cpu().numpy()
+    lmd = lm.astype(np.float64)
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        dsl = slice(int(offsets[s]), int(offsets[s + 1]))
+        ref = oracle.trajectory(h0[sl], ys[s] ** 2, rs[s], th[c], k, dt, seed=smp.pb.seed,
+                                sweep=6, chain=c, log_m=lmd[dsl])
+        assert abs(dh[c] - ref["dH"]) <= 1e-9 * max(1.0, abs(ref["dH"]))
+        if abs(ref["dH"] + oracle.log_u(smp.pb.seed, 6, c)) > NEAR_TIE:
+            assert bool(acc[c]) == ref["accepted"]
+            assert rel_inf(h_gpu[sl], ref["h"]) <= 1e-12
+
+
+def test_f32_mixed_trajectory_with_mass_error_vs_f64():
+    """FP32 leapfrog with a diagonal mass against the FP64 oracle on the same
+    (FP32-rounded) momenta and mass; bounds as for the identity-mass case."""
+    Ts, C, k, dt = [3000, 700], 2, 30, 0.08
+    lm = np.clip(2.4 + 0.7 * np.random.default_rng(5).standard_normal(sum(Ts)), -5, 5)
+    lm = lm.astype(np.float32)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, precision=RSV_F32_MIXED, log_mass=lm)
+    rng = np.random.default_rng(8)
+    p0 = rng.standard_normal(smp.n_state) * np.exp(0.5 * np.concatenate(
+        [np.tile(lm[offsets[s]:offsets[s + 1]], C) for s in range(len(Ts))]))
+    dh, acc = smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
+    h32 = smp.h.cpu().numpy().astype(np.float64)
+    h0_32 = h0.astype(np.float32).astype(np.float64)
+    lmd = lm.astype(np.float64)
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        dsl = slice(int(offsets[s]), int(offsets[s + 1]))
+        p0c = p0[sl].astype(np.float32).astype(np.float64)
+        h1, p1 = oracle.leapfrog(h0_32[sl], p0c, ys[s] ** 2, rs[s], th[c], k, dt,
+                                 log_m=lmd[dsl])
+        dH = oracle.delta_h(h0_32[sl], p0c, h1, p1, ys[s] ** 2, rs[s], th[c], log_m=lmd[dsl])
+        assert np.max(np.abs(h32[sl] - h1)) <= 2e-5
+        assert abs(dh[c].item() - dH) <= 2e-3 * np.sqrt(sl.stop - sl.start) / 30
+    assert bool(acc.all())
+
+
+@pytest.mark.parametrize("Ts,C", [([1000], 1), ([513, 4000], 2)])
+def test_trajectory_with_step_jitter_f64(Ts, C):
+    k, dt, j = 20, 0.05, 0.4
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, dtau_jitter=j)
+    dh, acc = smp.trajectory(12, (k, dt))
+    h_gpu, dh, acc = smp.h.cpu().numpy(), dh.cpu().numpy(), acc.cpu().numpy()
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        ref = oracle.trajectory(h0[sl], ys[s] ** 2, rs[s], th[c], k, dt, seed=smp.pb.seed,
+                                sweep=12, chain=c, jitter=j)
+        assert abs(dh[c] - ref["dH"]) <= 1e-9 * max(1.0, abs(ref["dH"]))
+        if abs(ref["dH"] + oracle.log_u(smp.pb.seed, 12, c)) > NEAR_TIE:
+            assert bool(acc[c]) == ref["accepted"]
+            assert rel_inf(h_gpu[sl], ref["h"]) <= 1e-12
+
+
+def test_sweep_with_step_jitter_matches_oracle():
+    Ts, C, k, dt, n, j = [600, 2500], 2, 30, 0.04, 40, 0.3
+    thetas = synth.draw_batch_thetas(len(Ts), 6)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, thetas=thetas, dtau_jitter=j)
+    out = smp.sweep(50, n, (k, dt), update_theta=True)
+    acc = out["accepted"].cpu().numpy()
+    dh = out["delta_h"].cpu().numpy()
+    tht = out["theta"].cpu().numpy()
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        ref = oracle.run(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, seed=smp.pb.seed,
+                         chain=c, first_sweep=50, jitter=j)
+        m = _compare_runs(acc[:, c], dh[:, c], tht[:, c], ref, smp.pb.seed, c, 50)
+        if m == n:
+            assert rel_inf(smp.h.cpu().numpy()[sl], ref["h"]) <= 1e-10
 
 
 def test_linear_gaussian_terms_f64():
@@ -294,8 +371,9 @@ def test_batch_mean_accumulators_match_recorded_trace():
     np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq, rtol=1e-14)
 
 
-@pytest.mark.parametrize("precision", [RSV_F64, RSV_F32_MIXED])
-def test_resident_sweeps_equal_per_kernel_sweeps(precision):
+@pytest.mark.parametrize("precision,dtau_jitter", [(RSV_F64, 0.0), (RSV_F32_MIXED, 0.0),
+                                                   (RSV_F64, 0.3)])
+def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter):
     """Chains that fit one tile run all sweeps in one launch; the result must
     be bitwise the one of one launch per kernel per sweep."""
     from paper_1603_08114_amd._lib import RSV_FLAG_NO_RESIDENT
@@ -308,7 +386,7 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision):
     for flags in (0, RSV_FLAG_NO_RESIDENT):
         smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                              chains_per_series=C, precision=precision, max_steps=k, seed=4,
-                             flags=flags)
+                             flags=flags, dtau_jitter=dtau_jitter)
         o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True, batch_len=7)
         o["state"] = smp.h.clone()
         o["theta_final"] = smp.theta.clone()

@@ -128,3 +128,33 @@ def test_creutz_identity():
     e = np.exp(-out["dH"][200:])
     mcse = batch_means_mcse(e)
     assert abs(e.mean() - 1.0) <= 3 * mcse, (e.mean(), mcse)
+
+
+def test_step_size_jitter_is_uniform_and_independent():
+    """dtau_i / dtau - 1 over sweeps is U(-j, j) (Kolmogorov-Smirnov), chains
+    draw independent factors, and j = 0 returns dtau exactly."""
+    j, dtau, n = 0.3, 0.05, 20000
+    f = np.array([oracle.step_size(9, s, 0, dtau, j) for s in range(n)]) / dtau - 1.0
+    assert np.all(np.abs(f) <= j)
+    assert stats.kstest(f, stats.uniform(loc=-j, scale=2 * j).cdf).pvalue > 1e-3
+    g = np.array([oracle.step_size(9, s, 1, dtau, j) for s in range(n)]) / dtau - 1.0
+    assert abs(np.corrcoef(f, g)[0, 1]) < 4.0 / np.sqrt(n)
+    assert all(oracle.step_size(9, s, 0, dtau, 0.0) == dtau for s in range(100))
+
+
+def test_jittered_long_trajectories_match_kalman_smoother():
+    """k dtau = 1 puts several Gaussian modes of the linear-Gaussian target
+    near a multiple of their half period, where a fixed-length sampler barely
+    moves them; with the step size jittered by +-50% every mode mixes and the
+    moments match the exact smoother (stationarity of the jittered chain)."""
+    T = 50
+    y, r, h_true = synth.simulate_rsv(T, TH, 31)
+    z = r - TH["xi"] - TH["mu"]
+    km, kv = kalman_rts(z, TH["phi"], TH["sig2_eta"], TH["sig2_u"])
+    out = oracle.run(h_true, TH, y * y, r, k=20, dtau=0.05, n_sweeps=60_000, seed=6,
+                     update_theta=False, terms=oracle.TERM_RV, keep_h=True, jitter=0.5)
+    assert out["accepted"].mean() > 0.6
+    draws = out["h_trace"][1000:]
+    zm, zv = z_scores_mean_var(draws, km + TH["mu"], kv)
+    assert z_rule_ok(zm), zm
+    assert z_rule_ok(zv), zv
