@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--sites-per-lane", type=int, default=8)
     ap.add_argument("--waves-per-tile", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--dtau-jitter", type=float, default=-1.0,
+                    help="step-size jitter j (dtau * U[1-j, 1+j] per trajectory); -1 = the "
+                         "workload's default (0 for the fixed-dtau long and small workloads, "
+                         "0.5 for batched, mass and the precision study's chains)")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
     ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "precision"],
@@ -179,9 +183,10 @@ def run_small(args):
     import synth
     from paper_1603_08114_amd import api
     T, k, dtau, burn, n = 1000, 20, 0.05, 500, 5000
+    jit = jitter_of(args, 0.0)
     theta = dict(synth.THETA_STAR)
     y, lr, h_true = synth.simulate_rsv(T, theta, 1)
-    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1)
+    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1, dtau_jitter=jit)
     smp.sweep(0, burn, (k, dtau), update_theta=True, record=())
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -199,8 +204,9 @@ def run_small(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": "single-series RSV HMC, T=1000, k=20, dtau=0.05, FP64, "
-                                  "500 burn-in + 5000 sweeps, theta every sweep",
-                      "T": T, "k": k, "dtau": dtau, "chains": 1},
+                                  "500 burn-in + 5000 sweeps, theta every sweep"
+                                  + (f", dtau jitter {jit}" if jit else ""),
+                      "T": T, "k": k, "dtau": dtau, "dtau_jitter": jit, "chains": 1},
            "site_updates_per_s": T * k * n / elapsed, "min_ess": min_ess,
            "min_ess_theta": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
                                      map(float, ess_th))),
@@ -209,7 +215,8 @@ def run_small(args):
         import time as _t
         import oracle
         t0 = _t.perf_counter()
-        ref = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True)
+        ref = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True,
+                         jitter=jit)
         dt = _t.perf_counter() - t0
         m_ref, _, _ = min_ess_from_traces(ref["h_trace"][burn:], ref["theta_trace"][burn:])
         res["cpu_baseline"] = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s",
@@ -220,11 +227,16 @@ def run_small(args):
     return res
 
 
+def jitter_of(args, default):
+    return default if args.dtau_jitter < 0 else args.dtau_jitter
+
+
 def run_batched(args):
     """512 series, T ~ U{500..8000}, per-series theta, 4 chains each, k = 30,
-    FP32-mixed leapfrog; per-series dtau adapted to ~0.8 acceptance over 500
-    warm-up sweeps; 2000 measured sweeps with batch means (50 batches of 40)
-    accumulated on the device.  value = median over series of min-ESS/s."""
+    FP32-mixed leapfrog, step size jittered +-50%; per-series dtau adapted to
+    ~0.8 acceptance over 500 warm-up sweeps; 2000 measured sweeps with batch
+    means (50 batches of 40) accumulated on the device.  value = median over
+    series of min-ESS/s."""
     import torch
     import synth
     from paper_1603_08114_amd import api, diagnostics
@@ -235,8 +247,9 @@ def run_batched(args):
     Ts = np.diff(off)
     h0 = np.concatenate([np.tile(data["h_true"][off[s]:off[s + 1]], C_) for s in range(S_)])
     thetas = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
+    jit = jitter_of(args, 0.5)
     smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, chains_per_series=C_,
-                         precision=RSV_F32_MIXED, max_steps=k, seed=3)
+                         precision=RSV_F32_MIXED, max_steps=k, seed=3, dtau_jitter=jit)
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
     sweep = 0
     for _ in range(10):  # 10 windows of 50 warm-up sweeps
@@ -282,8 +295,10 @@ def run_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32-mixed", "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": "batched RSV HMC: 512 series, T~U{500..8000}, 4 chains each, "
-                                  "k=30, FP32 leapfrog, FP64 dH/theta, 2000 sweeps",
-                      "series": S_, "chains_per_series": C_, "k": k, "total_sites": int(Ts.sum())},
+                                  f"k=30, dtau jitter {jit}, FP32 leapfrog, FP64 dH/theta, "
+                                  "2000 sweeps",
+                      "series": S_, "chains_per_series": C_, "k": k, "dtau_jitter": jit,
+                      "total_sites": int(Ts.sum())},
            "min_over_series": float(rate.min()), "site_updates_per_s": total_su / elapsed,
            "acceptance": float(out["accepted"].float().mean().item()),
            "dtau_range": [float(dtau.min()), float(dtau.max())]}
@@ -297,7 +312,7 @@ def run_batched(args):
         t0 = _t.perf_counter()
         for j in range(C_):
             oracle.run(data["h_true"][off[s]:off[s + 1]], data["thetas"][s], y2, r, k,
-                       float(dtau[s]), 25, seed=3, chain=s * C_ + j)
+                       float(dtau[s]), 25, seed=3, chain=s * C_ + j, jitter=jit)
         dt = _t.perf_counter() - t0
         res["cpu_baseline"] = {"value": T * k * 25 * C_ / dt, "unit": "site-updates/s",
                                "cores": 1, "kind": "oracle",
@@ -322,7 +337,8 @@ def run_mass(args):
     train = synth.make_batch(n_train, 500, 8000, seed=4)
     held = synth.make_batch(n_held, 1000, 16000, seed=5)
     print(f"[mass] training targets from {n_train} series", file=sys.stderr, flush=True)
-    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000)
+    jit = jitter_of(args, 0.5)
+    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000, dtau_jitter=jit)
     target = -torch.log(torch.clamp(tr["var"], min=1e-12))
     net, hist, r2 = LM.train_network(train, target, tr["theta_mean"], epochs=30)
     print(f"[mass] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, R^2 {r2:.3f}", file=sys.stderr,
@@ -332,7 +348,7 @@ def run_mass(args):
     out = {}
     res_arm = {}
     for name, (prec, nt) in arms.items():
-        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25)
+        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25, dtau_jitter=jit)
         res_arm[name] = r
         per = np.minimum(r["ess_h"], r["ess_theta"]) / r["elapsed"]
         out[name] = {"median_min_ess_per_s": float(np.median(per)),
@@ -350,7 +366,7 @@ def run_mass(args):
     for name, (prec, nt, sd) in {"identity_f64": (RSV_F64, None, 6),
                                  "learned_f32": (RSV_F32_MIXED, net, 7)}.items():
         fixed[name] = LM.run_arm(held, C, k, prec, nt, seed=sd, warm=500, n=1000, bl=25,
-                                 update_theta=False)
+                                 update_theta=False, dtau_jitter=jit)
     a, b = fixed["identity_f64"], fixed["learned_f32"]
     z = ((b["mean"] - a["mean"]) / torch.sqrt(a["mcse2"] + b["mcse2"])).cpu().numpy()
     z = z[np.isfinite(z)]
@@ -365,8 +381,9 @@ def run_mass(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed + bf16 network",
            "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": f"learned diagonal mass: train {n_train} series, evaluate "
-                                  f"{n_held} held-out series x 4 chains, k=30",
-                      "train_series": n_train, "held_out_series": n_held, "k": k},
+                                  f"{n_held} held-out series x 4 chains, k=30, dtau jitter {jit}",
+                      "train_series": n_train, "held_out_series": n_held, "k": k,
+                      "dtau_jitter": jit},
            "arms": out, "gain_learned_f32_vs_identity_f64": gain,
            "training": {"loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "r2": r2},
            "fixed_theta_h_means_learned_f32_vs_identity_f64": {
@@ -422,7 +439,8 @@ def run_precision(args):
     for upd in (False, True):
         for prec, sd in ((RSV_F32_MIXED, 1), (RSV_F64, 2)):
             smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k,
-                                 seed=args.seed + sd + (10 if upd else 0), precision=prec)
+                                 seed=args.seed + sd + (10 if upd else 0), precision=prec,
+                                 dtau_jitter=jitter_of(args, 0.5))
             smp.sweep(0, 200, lf, update_theta=upd, record=())
             o = smp.sweep(200, n_chain, lf, update_theta=upd, record=("theta",), batch_len=bl)
             bm = o["h_batch_sum"] / bl
@@ -492,9 +510,10 @@ def main():
     theta = dict(synth.THETA_STAR)
     y, lr, h_true = synth.simulate_rsv_long(T, theta, args.seed)
     prec = RSV_F64 if args.precision == "f64" else RSV_F32_MIXED
+    jit = jitter_of(args, 0.0)
     smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
                          precision=prec, sites_per_lane=args.sites_per_lane,
-                         waves_per_tile=args.waves_per_tile)
+                         waves_per_tile=args.waves_per_tile, dtau_jitter=jit)
     S, NW = args.sites_per_lane, args.waves_per_tile
     print(f"[bench] T={T} k={k} precision={args.precision} S={S} NW={NW}", file=sys.stderr,
           flush=True)
@@ -550,7 +569,7 @@ def main():
         roof["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
         roof["traffic_detail"] = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
                                   "per": "k_traj launch (one trajectory)",
-                                  "algorithmic_bytes": 40.0 * T if args.precision == "f64" else 20.0 * T}
+                                  "algorithmic_bytes": 32.0 * T}
     stream_gbs = STREAM_BYTES[args.precision] * traj_rate / 1e9
 
     res = {
@@ -568,8 +587,8 @@ def main():
         "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
         "config": {"workload": f"single-series RSV HMC sweep, T={T}, k={k}, "
                                f"{args.precision.upper()}, theta updated every sweep",
-                   "T": T, "k": k, "dtau": dtau, "chains": 1, "sites_per_lane": S,
-                   "waves_per_tile": NW},
+                   "T": T, "k": k, "dtau": dtau, "dtau_jitter": jit, "chains": 1,
+                   "sites_per_lane": S, "waves_per_tile": NW},
         "roofline": roof,
         "acceptance": acc_rate,
         "traj_kernel_site_updates_per_s": traj_rate,

@@ -108,7 +108,8 @@ def chains_for(data, C):
     return h0, thetas
 
 
-def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True):
+def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True,
+            dtau_jitter=0.0):
     """One arm on one batch of series; returns measure() output plus dtau.
     update_theta=False holds every chain at its series' generating theta (an
     exactness check of the h update alone: the h-conditional mixes in a few
@@ -117,7 +118,8 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
     S = len(off) - 1
     Ts = np.diff(off)
     h0, thetas = chains_for(data, C)
-    kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed)
+    kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed,
+              dtau_jitter=dtau_jitter)
     smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, **kw)
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
     dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 100, S, C,
@@ -140,9 +142,10 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
     return res
 
 
-def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0):
+def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0, dtau_jitter=0.0):
     """Pooled per-site posterior mean and variance from identity FP64 chains."""
-    res = run_arm(data, C, k, RSV_F64, None, seed=seed, warm=warm, n=n, bl=40)
+    res = run_arm(data, C, k, RSV_F64, None, seed=seed, warm=warm, n=n, bl=40,
+                  dtau_jitter=dtau_jitter)
     return res
 
 
