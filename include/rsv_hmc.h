@@ -101,9 +101,9 @@ typedef struct {
                                    held by each lane (0 = library default;
                                    RSV_F64: 4 or 8, RSV_F32_MIXED: 8 or 16)    */
     int32_t waves_per_tile;     /* wavefronts per tile (0 = default 4; compiled
-                                   (S, NW): F64 (4,1) (4,4) (8,1) (8,2) (8,4)
-                                   (8,8); F32 (8,1) (8,4) (8,8) (16,1) (16,2)
-                                   (16,4)).
+                                   (S, NW): F64 S in {4, 8} x NW in {1, 2, 4,
+                                   8}; F32 S = 8 x NW in {1, 2, 4, 8} and
+                                   S = 16 x NW in {1, 2, 4}).
                                    A tile spans 64 * waves_per_tile *
                                    sites_per_lane sites, of which all but a
                                    k+1 halo on each cut side are exact          */

@@ -20,8 +20,8 @@ import torch
 from . import api
 from ._lib import RSV_F64
 
-SHAPES = {RSV_F64: [(4, 1), (4, 4), (8, 1), (8, 2), (8, 4), (8, 8)],
-          1: [(8, 1), (8, 4), (8, 8), (16, 1), (16, 2), (16, 4)]}
+SHAPES = {RSV_F64: [(4, 1), (4, 2), (4, 4), (4, 8), (8, 1), (8, 2), (8, 4), (8, 8)],
+          1: [(8, 1), (8, 2), (8, 4), (8, 8), (16, 1), (16, 2), (16, 4)]}
 
 
 def _bucket(x):

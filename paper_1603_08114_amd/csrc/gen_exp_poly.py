@@ -55,7 +55,7 @@ def remez(deg, a, iters=30):
 
 
 def main():
-    deg = int(sys.argv[1]) if len(sys.argv) > 1 else 11
+    deg = int(sys.argv[1]) if len(sys.argv) > 1 else 10
     a = mp.log(2) / 2 * mp.mpf("1.0001")
     coef = remez(deg, a)
     c64 = [float(c) for c in coef]

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rsv_exp.h"
+
 namespace rsv {
 
 constexpr int kWave = 64;
@@ -63,9 +65,9 @@ __device__ inline void uniforms4(uint64_t seed, uint64_t idx, uint64_t sweep, ui
 
 // Box-Muller on one pair: radius sqrt(-2 ln u0), angle 2 pi u1.
 __device__ inline void gauss_pair(double u0, double u1, double& z0, double& z1) {
-    const double radius = sqrt(-2.0 * log(u0));
+    const double radius = sqrt(-2.0 * log_unit(u0));
     double s, c;
-    sincos(6.283185307179586 * u1, &s, &c);
+    sincos_2pi(u1, s, c);
     z0 = radius * c;
     z1 = radius * s;
 }

@@ -1,42 +1,121 @@
-// rsv_exp.h -- exponentials for the leapfrog force (the e^{-h_t} y_t^2 term).
+// rsv_exp.h -- elementary functions of the trajectory kernel.
 //
 // The force needs e^{-h} once per site-update; it dominates the instruction
-// count of the trajectory kernel.  These versions drop the library's explicit
-// overflow / underflow range checks: v_ldexp saturates to +inf / 0 by itself,
-// which gives the same results for finite inputs beyond the range; a NaN input
-// gives NaN.  (For |x| so large that the reduction itself overflows -- far
-// beyond any state a trajectory can accept -- the result is NaN instead of
-// inf, and the trajectory is rejected either way.)
+// count of the trajectory kernel.  The per-trajectory parts (momentum draw,
+// dH terms) use the same kind of short, branch-free versions instead of the
+// library's functions, which carry range checks and large-argument paths
+// that the arguments here never need.  None of these functions raises or
+// branches on its argument; a NaN argument gives NaN (and a NaN dH rejects
+// the trajectory).  A leapfrog is volume preserving and reversible for any
+// force that is a function of position alone, so the few-ulp differences
+// from the library change nothing about the exactness of the chain.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace rsv {
 
-// e^x in FP64: x = n ln2 + r, |r| <= ln2/2, e^x = 2^n P(r).  ln2 is split into
-// its FP64 value and the rounding remainder so that r carries ~1 ulp.  P is the
-// degree-11 minimax polynomial for e^r (relative error 1.7e-17 after rounding
-// the coefficients; gen_exp_poly.py).
+// e^x in FP64: x = n ln2 + r, |r| <= ln2/2, e^x = 2^n P(r).  n is rounded by
+// adding 1.5 * 2^52 (the sum's low word then holds n as an integer), ln2 is
+// split into its FP64 value and the rounding remainder so that r carries
+// ~1 ulp, P is the degree-10 minimax polynomial for e^r (relative error
+// 3.3e-16 after rounding the coefficients; gen_exp_poly.py), and 2^n is
+// applied by adding n to the exponent field.  n is clamped to [-1022, 1023]:
+// beyond |x| ~ 708 the result is a finite number of the right sign and side
+// (tiny or huge) instead of 0 or inf.  Worst relative error on |x| <= 700:
+// 4.7e-16 (4 ulp).
 __device__ __forceinline__ double exp_fast(double x) {
     const double log2e = 0x1.71547652b82fep+0;
     const double ln2_hi = 0x1.62e42fefa39efp-1;
     const double ln2_lo = 0x1.abc9e3b39803fp-56;
-    const double n = __builtin_rint(x * log2e);
+    const double shift = 0x1.8p52;
+    const double t = __builtin_fma(x, log2e, shift);
+    const double n = t - shift;
     double r = __builtin_fma(-n, ln2_hi, x);
     r = __builtin_fma(-n, ln2_lo, r);
-    double p = 2.4995873031469468e-08;
-    p = __builtin_fma(p, r, 2.7632471742635444e-07);
-    p = __builtin_fma(p, r, 2.7557617915243222e-06);
-    p = __builtin_fma(p, r, 2.4801485990990488e-05);
-    p = __builtin_fma(p, r, 0.00019841269437402027);
-    p = __builtin_fma(p, r, 0.0013888888951775489);
-    p = __builtin_fma(p, r, 0.00833333333355733);
-    p = __builtin_fma(p, r, 0.04166666666649043);
-    p = __builtin_fma(p, r, 0.16666666666666172);
-    p = __builtin_fma(p, r, 0.5000000000000018);
+    double p = 2.749029984051582e-07;
+    p = __builtin_fma(p, r, 2.763997818821441e-06);
+    p = __builtin_fma(p, r, 2.480191277326453e-05);
+    p = __builtin_fma(p, r, 0.00019841170822930575);
+    p = __builtin_fma(p, r, 0.0013888888503440534);
+    p = __builtin_fma(p, r, 0.008333333385165677);
+    p = __builtin_fma(p, r, 0.04166666666841235);
+    p = __builtin_fma(p, r, 0.16666666666556093);
+    p = __builtin_fma(p, r, 0.49999999999997297);
+    p = __builtin_fma(p, r, 1.0000000000000067);
     p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+    int ni = __double2loint(t);
+    ni = ni < -1022 ? -1022 : (ni > 1023 ? 1023 : ni);
+    return __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
+}
+
+// e^x - 1 with an absolute (not relative) error of a few ulp of max(1, e^x):
+// enough wherever the result is multiplied into a sum of O(1) terms.
+__device__ __forceinline__ double expm1_abs(double x) { return exp_fast(x) - 1.0; }
+
+// ln u for u in (0, 1]: u = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716, by its Taylor
+// series through s^19 (truncation < 3e-17 relative).
+__device__ __forceinline__ double log_unit(double u) {
+    int e = __builtin_amdgcn_frexp_exp(u);
+    double m = __builtin_amdgcn_frexp_mant(u);  // [0.5, 1)
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double q = 2.0 / 19.0;
+    q = __builtin_fma(q, s2, 2.0 / 17.0);
+    q = __builtin_fma(q, s2, 2.0 / 15.0);
+    q = __builtin_fma(q, s2, 2.0 / 13.0);
+    q = __builtin_fma(q, s2, 2.0 / 11.0);
+    q = __builtin_fma(q, s2, 2.0 / 9.0);
+    q = __builtin_fma(q, s2, 2.0 / 7.0);
+    q = __builtin_fma(q, s2, 2.0 / 5.0);
+    q = __builtin_fma(q, s2, 2.0 / 3.0);
+    const double ln2_hi = 0x1.62e42fefa39efp-1;
+    const double ln2_lo = 0x1.abc9e3b39803fp-56;
+    const double de = static_cast<double>(e);
+    // ln m = 2s + s^3 q
+    const double lnm = __builtin_fma(s * s2, q, 2.0 * s);
+    return __builtin_fma(de, ln2_hi, __builtin_fma(de, ln2_lo, lnm));
+}
+
+// sin and cos of 2 pi u for u in [0, 1]: 4u = k + r exactly (k integer,
+// |r| <= 1/2), angle th = r pi/2 in [-pi/4, pi/4] from a two-part pi/2,
+// Taylor series through th^17 (sin) and th^16 (cos), then the quadrant k.
+__device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
+    const double x4 = 4.0 * u;
+    const double k = __builtin_rint(x4);
+    const double r = x4 - k;
+    const double pio2_hi = 0x1.921fb54442d18p+0;
+    const double pio2_lo = 0x1.1a62633145c07p-54;
+    const double th = __builtin_fma(r, pio2_hi, r * pio2_lo);
+    const double t2 = th * th;
+    double ps = 1.0 / 355687428096000.0;           // 1/17!
+    ps = __builtin_fma(ps, t2, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, t2, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, t2, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, t2, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, t2, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, t2, 1.0 / 120.0);
+    ps = __builtin_fma(ps, t2, -1.0 / 6.0);
+    const double s = __builtin_fma(th * t2, ps, th);
+    double pc = 1.0 / 20922789888000.0;            // 1/16!
+    pc = __builtin_fma(pc, t2, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, t2, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, t2, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, t2, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, t2, -1.0 / 720.0);
+    pc = __builtin_fma(pc, t2, 1.0 / 24.0);
+    pc = __builtin_fma(pc, t2, -0.5);
+    const double c = __builtin_fma(t2, pc, 1.0);
+    const int q = static_cast<int>(k) & 3;
+    const double s_sel = (q & 1) ? c : s;
+    const double c_sel = (q & 1) ? s : c;
+    sn = (q & 2) ? -s_sel : s_sel;
+    cs = ((q + 1) & 2) ? -c_sel : c_sel;
 }
 
 // e^x in FP32: 2^h with h = x log2 e rounded, times e^r for the residual

@@ -109,7 +109,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         for (int j = 0; j < S; ++j) {
             const int t = t0 + j;
             const double l = (t < T) ? static_cast<double>(lm[t]) : 0.0;
-            dtm[j] = static_cast<R>(dt * exp(-l));
+            dtm[j] = static_cast<R>(dt * exp_fast(-l));
         }
     }
     if (A.p0) {
@@ -132,7 +132,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
                 const int j = 4 * g + q;
                 const int t = t0 + j;
                 double pm = z[q];
-                if constexpr (MASS) pm *= exp(0.5 * ((t < T) ? static_cast<double>(lm[t]) : 0.0));
+                if constexpr (MASS) pm *= exp_fast(0.5 * ((t < T) ? static_cast<double>(lm[t]) : 0.0));
                 p[j] = (t < T) ? static_cast<R>(pm) : R(0);
             }
         }
@@ -142,7 +142,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const int t = t0 + j;
         if (t >= td.a && t < td.b) {
             const double pj = static_cast<double>(p[j]);
-            const double im = MASS ? exp(-static_cast<double>(lm[t])) : 1.0;
+            const double im = MASS ? exp_fast(-static_cast<double>(lm[t])) : 1.0;
             kin0 += 0.5 * pj * pj * im;
         }
     }
@@ -226,10 +226,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const double h1 = static_cast<double>(h[j]);
         const double h0 = h0d[j];
         const double pj = static_cast<double>(p[j]);
-        const double im = MASS ? exp(-static_cast<double>(lm[t])) : 1.0;
+        const double im = MASS ? exp_fast(-static_cast<double>(lm[t])) : 1.0;
         const double rr = lrd[t];
         double d = 0.5 * pj * pj * im;
-        if (RET) d += 0.5 * (h1 - h0) + 0.5 * y2d[t] * exp(-h0) * expm1(h0 - h1);
+        if (RET) d += 0.5 * (h1 - h0) + 0.5 * y2d[t] * exp_fast(-h0) * expm1_abs(h0 - h1);
         if (rv) {
             const double c = rr - xi;
             const double e1 = c - h1, e0 = c - h0;
@@ -290,10 +290,21 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     }
 }
 
+// Occupancy hint of the trajectory kernel (waves per SIMD; 0 = compiler's
+// choice).  Set at build time.
+#ifndef RSV_TRAJ_WAVES_PER_EU
+#define RSV_TRAJ_WAVES_PER_EU 0
+#endif
+#if RSV_TRAJ_WAVES_PER_EU > 0
+#define RSV_TRAJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RSV_TRAJ_WAVES_PER_EU)))
+#else
+#define RSV_TRAJ_OCCUPANCY
+#endif
+
 // One launch covers every tile; tiles whose chain ends inside a lane (EDGE)
 // take the variant that substitutes the end-point neighbour per site.
 template <typename R, int S, int NW, bool MASS, bool RET>
-__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void k_traj(TrajArgs<R> A) {
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) RSV_TRAJ_OCCUPANCY void k_traj(TrajArgs<R> A) {
     static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
     static_assert(NW == 1 || NW == 2 || NW == 4 || NW == 8, "tile shapes");
     // NW = 1: four independent tiles per 256-thread block (no barriers);
@@ -676,7 +687,7 @@ __global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const 
         for (int q = 0; q < 4; ++q) {
             const int t = 4 * g + q;
             if (t >= cd.T) break;
-            const double sm = log_mass ? exp(0.5 * static_cast<double>(log_mass[cd.d_off + t])) : 1.0;
+            const double sm = log_mass ? exp_fast(0.5 * static_cast<double>(log_mass[cd.d_off + t])) : 1.0;
             p_out[cd.h_off + t] = z[q] * sm;
         }
     }
@@ -728,9 +739,9 @@ hipError_t launch_traj_t(hipStream_t st, bool mass, bool ret, const TrajArgs<R>&
 // Tile shapes compiled for each precision: (sites per lane, wavefronts per
 // tile); the first is the default.
 bool traj_shape_available(int precision, int S, int NW) {
-    if (precision == RSV_F64)
-        return (S == 4 && (NW == 1 || NW == 4)) || (S == 8 && (NW == 1 || NW == 2 || NW == 4 || NW == 8));
-    return (S == 8 && (NW == 1 || NW == 4 || NW == 8)) || (S == 16 && (NW == 1 || NW == 2 || NW == 4));
+    const bool nw = NW == 1 || NW == 2 || NW == 4 || NW == 8;
+    if (precision == RSV_F64) return nw && (S == 4 || S == 8);
+    return (S == 8 && nw) || (S == 16 && (NW == 1 || NW == 2 || NW == 4));
 }
 void traj_default_shape(int precision, int* S, int* NW) {
     *S = 8;
@@ -744,7 +755,9 @@ hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
         const auto& a = *static_cast<const TrajArgs<double>*>(args);
         const bool ret = (a.terms & RSV_TERM_RETURN) != 0;
         if (S == 4 && NW == 1) return launch_traj_t<double, 4, 1>(st, mass, ret, a);
+        if (S == 4 && NW == 2) return launch_traj_t<double, 4, 2>(st, mass, ret, a);
         if (S == 4 && NW == 4) return launch_traj_t<double, 4, 4>(st, mass, ret, a);
+        if (S == 4 && NW == 8) return launch_traj_t<double, 4, 8>(st, mass, ret, a);
         if (S == 8 && NW == 1) return launch_traj_t<double, 8, 1>(st, mass, ret, a);
         if (S == 8 && NW == 2) return launch_traj_t<double, 8, 2>(st, mass, ret, a);
         if (S == 8 && NW == 4) return launch_traj_t<double, 8, 4>(st, mass, ret, a);
@@ -753,6 +766,7 @@ hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
         const auto& a = *static_cast<const TrajArgs<float>*>(args);
         const bool ret = (a.terms & RSV_TERM_RETURN) != 0;
         if (S == 8 && NW == 1) return launch_traj_t<float, 8, 1>(st, mass, ret, a);
+        if (S == 8 && NW == 2) return launch_traj_t<float, 8, 2>(st, mass, ret, a);
         if (S == 8 && NW == 4) return launch_traj_t<float, 8, 4>(st, mass, ret, a);
         if (S == 8 && NW == 8) return launch_traj_t<float, 8, 8>(st, mass, ret, a);
         if (S == 16 && NW == 1) return launch_traj_t<float, 16, 1>(st, mass, ret, a);

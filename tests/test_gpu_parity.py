@@ -77,7 +77,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("Ts,C,k,dt", SHAPES)
-@pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 4), (8, 2), (8, 4), (8, 8)])
+@pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4), (8, 8)])
 def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
     smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW)
     rng = np.random.default_rng(3)
@@ -417,7 +417,7 @@ def test_tile_shapes_give_the_same_trajectory():
     trajectory is bitwise equal across tile shapes."""
     k, dt = 30, 0.03
     outs = []
-    for S, NW in [(4, 1), (8, 1), (4, 4), (8, 2), (8, 4), (8, 8)]:
+    for S, NW in [(4, 1), (8, 1), (4, 2), (4, 4), (4, 8), (8, 2), (8, 4), (8, 8)]:
         smp, offsets, ys, rs, h0, th = sampler([5000, 1200], 2, k=k, S=S, NW=NW)
         p0 = np.random.default_rng(2).standard_normal(h0.size)
         smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
