@@ -26,7 +26,7 @@ __device__ inline R ghost_neighbour(R h, R mu, R phi) {
 template <typename R>
 __device__ inline R exp_neg(R x);
 template <>
-__device__ inline double exp_neg<double>(double x) { return exp_fast(-x); }
+__device__ inline double exp_neg<double>(double x) { return exp_force(-x); }
 template <>
 __device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
 
