@@ -66,12 +66,24 @@ typedef enum { RSV_F64 = 0, RSV_F32_MIXED = 1 } rsv_precision;
  * updated. */
 enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
 
-/* Execution flags.  By default rsv_hmc_sweep runs every sweep of a call in a
- * single launch when each chain fits one tile of four wavefronts (the chain
- * stays resident in one block: trajectory, dH, Metropolis and theta update
- * separated by block barriers); RSV_FLAG_NO_RESIDENT forces one launch per
- * kernel per sweep instead.  Results are identical either way. */
-enum { RSV_FLAG_NO_RESIDENT = 1 };
+/* Flags.
+ * RSV_FLAG_NO_RESIDENT: by default rsv_hmc_sweep runs every sweep of a call
+ *   in a single launch when each chain fits one tile of four wavefronts (the
+ *   chain stays resident in one block: trajectory, dH, Metropolis and theta
+ *   update separated by block barriers); this flag forces one launch per
+ *   kernel per sweep instead.  Results are identical either way.
+ * RSV_FLAG_LEVEL_MOVE: every theta update (rsv_hmc_sweep with update_theta,
+ *   rsv_theta_update) first moves the whole state along h_t -> h_t + c,
+ *   mu -> mu + c, xi -> xi - c (xi only with RSV_TERM_RV).  That direction
+ *   leaves the AR(1) part and the RV residuals unchanged; with the return
+ *   term e^{-c} is drawn from Gamma(T/2, rate S/2), S = sum_t y_t^2 e^{-h_t},
+ *   and the prior ratio of mu (and xi) is the Metropolis test; without it c
+ *   is drawn from the Gaussian prior factors.  Random numbers: Philox stream
+ *   tag 4, block 0 (Box-Muller z from u0, u1; u2 the test), Gamma attempts
+ *   in blocks 1..32.  An extension: the paper's method updates h only, and
+ *   the Gibbs theta step alone mixes slowly along this direction (xi + h_t is
+ *   pinned by ln RV_t).  Off by default. */
+enum { RSV_FLAG_NO_RESIDENT = 1, RSV_FLAG_LEVEL_MOVE = 2 };
 
 /* theta of Sec. 2. */
 typedef struct { double phi, mu, xi, sig2_eta, sig2_u; } rsv_theta;

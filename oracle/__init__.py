@@ -72,8 +72,10 @@ def _load():
                                    P(C.c_int)]),
         "orc_neumaier_sum": (C.c_double, [_I64, _D]),
         "orc_step_size": (C.c_double, [_U64, _U64, _U64, C.c_double, C.c_double]),
+        "orc_level_move": (C.c_int, [_I64, _D, P(Theta), _D, P(Prior), C.c_int, _U64, _U64,
+                                     _U64, _D]),
         "orc_run": (_I64, [_I64, _D, P(Theta), _D, _D, _D, P(Prior), C.c_int, C.c_int32,
-                           C.c_double, C.c_double, _U64, _U64, _U64, _I64, C.c_int, _D,
+                           C.c_double, C.c_double, C.c_int, _U64, _U64, _U64, _I64, C.c_int, _D,
                            P(C.c_int32), P(Theta), _D]),
     }
     for name, (res, args) in sig.items():
@@ -228,6 +230,22 @@ def theta_update(T, stats, theta, seed, sweep, chain, prior=None, terms=TERMS_RS
     return out.as_dict(), flags
 
 
+MOVE_LEVEL = 2
+TAG_MOVE = 4
+
+
+def level_move(h, theta, y2, seed, sweep, chain, prior=None, terms=TERMS_RSV):
+    """The level move on (h, theta).  Returns dict(h, theta, flags, c)."""
+    h = _arr(h).copy(); T = h.size
+    th = theta_struct(theta)
+    th = Theta(*[getattr(th, k_) for k_ in THETA_KEYS])
+    c_out = np.zeros(1)
+    flags = _lib.orc_level_move(T, _ptr(h), C.byref(th), _ptr(_arr(y2, T)),
+                                C.byref(prior_struct(prior)), terms, seed, sweep, chain,
+                                _ptr(c_out))
+    return dict(h=h, theta=th.as_dict(), flags=flags, c=float(c_out[0]))
+
+
 def draw_mu(T, stats, theta, z, prior=None):
     return _lib.orc_draw_mu(int(T), _ptr(_arr(stats, 7)), C.byref(theta_struct(theta)),
                             C.byref(prior_struct(prior)), float(z))
@@ -250,7 +268,8 @@ def neumaier_sum(x):
 
 
 def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
-        update_theta=True, prior=None, terms=TERMS_RSV, log_m=None, keep_h=False, jitter=0.0):
+        update_theta=True, prior=None, terms=TERMS_RSV, log_m=None, keep_h=False, jitter=0.0,
+        moves=0):
     """n sweeps of one chain.  Returns dict with final h/theta and traces."""
     h = _arr(h).copy(); T = h.size
     th = theta_struct(theta)
@@ -262,8 +281,8 @@ def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
     htrace = np.zeros((n_sweeps, T)) if keep_h else None
     n_acc = _lib.orc_run(T, _ptr(h), C.byref(th), _ptr(lm), _ptr(_arr(y2, T)),
                          _ptr(_arr(r, T)), C.byref(prior_struct(prior)), terms, int(k),
-                         float(dtau), float(jitter), seed, chain, first_sweep, n_sweeps,
-                         int(update_theta),
+                         float(dtau), float(jitter), int(moves), seed, chain, first_sweep,
+                         n_sweeps, int(update_theta),
                          _ptr(dH), acc.ctypes.data_as(C.POINTER(C.c_int32)), ttrace,
                          _ptr(htrace))
     theta_tr = np.array([[getattr(ttrace[i], k_) for k_ in THETA_KEYS]

@@ -439,10 +439,69 @@ int orc_theta_update(int64_t T, const double st[7], const orc_theta *th_in,
     return flags;
 }
 
+/* ------------------------------------------------------------------ */
+/* Level move (an extension; see the header).                          */
+/* ------------------------------------------------------------------ */
+enum { MOVE_IDX_GAMMA = 1 };
+
+static double log_normal_kernel(double x, double mean, double var)
+{
+    double d = x - mean;
+    return -0.5 * d * d / var;
+}
+
+int orc_level_move(int64_t T, double *h, orc_theta *th, const double *y2, const orc_prior *pr,
+                   int terms, uint64_t seed, uint64_t sweep, uint64_t chain, double *c_out)
+{
+    const uint64_t tag = ORC_TAG_MOVE;
+    const int ret = (terms & ORC_TERM_RETURN) != 0, rv = (terms & ORC_TERM_RV) != 0;
+    const double n = (double)T;
+    int flags = 0;
+    double u[4], z_c, unused;
+    (void)unused;
+    orc_uniforms4(seed, 0, sweep, chain, tag, u);
+    box_muller(u[0], u[1], &z_c, &unused);
+    double c_applied = 0.0;
+    {
+        double c;
+        int accept;
+        if (ret) {
+            nsum sy = { 0, 0 };
+            for (int64_t t = 0; t < T; ++t) nsum_add(&sy, y2[t] * exp(-h[t]));
+            int exhausted = 0;
+            double g = orc_gamma(0.5 * n, seed, sweep, chain, tag, MOVE_IDX_GAMMA, &exhausted);
+            if (exhausted) flags |= 4;
+            c = -log(2.0 * g / nsum_value(&sy));
+            double log_a = log_normal_kernel(th->mu + c, pr->mu_mean, pr->mu_var)
+                         - log_normal_kernel(th->mu, pr->mu_mean, pr->mu_var);
+            if (rv)
+                log_a += log_normal_kernel(th->xi - c, pr->xi_mean, pr->xi_var)
+                       - log_normal_kernel(th->xi, pr->xi_mean, pr->xi_var);
+            accept = isfinite(c) && log(u[2]) < log_a;
+        } else {
+            /* Gaussian in c: N(mu + c; m_mu, v_mu) [N(xi - c; m_xi, v_xi)] */
+            double prec = 1.0 / pr->mu_var + (rv ? 1.0 / pr->xi_var : 0.0);
+            double lin = (pr->mu_mean - th->mu) / pr->mu_var
+                       + (rv ? (th->xi - pr->xi_mean) / pr->xi_var : 0.0);
+            c = lin / prec + z_c / sqrt(prec);
+            accept = 1;
+        }
+        if (accept) {
+            for (int64_t t = 0; t < T; ++t) h[t] += c;
+            th->mu += c;
+            if (rv) th->xi -= c;
+            c_applied = c;
+            flags |= 2;
+        }
+    }
+    if (c_out) *c_out = c_applied;
+    return flags;
+}
+
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, double jitter, uint64_t seed, uint64_t chain,
-                uint64_t first_sweep, int64_t n_sweeps, int update_theta,
+                int32_t k, double dtau, double jitter, int moves, uint64_t seed,
+                uint64_t chain, uint64_t first_sweep, int64_t n_sweeps, int update_theta,
                 double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
                 double *h_trace)
 {
@@ -455,6 +514,8 @@ int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                                  NULL, NULL, NULL, &dH);
         n_acc += acc;
         if (update_theta) {
+            if (moves & ORC_MOVE_LEVEL)
+                orc_level_move(T, h, th, y2, pr, terms, seed, sweep, chain, NULL);
             double st[7];
             orc_suffstats(T, h, r, th->mu, th->xi, st);
             orc_theta next;

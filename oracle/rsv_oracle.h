@@ -43,7 +43,11 @@ typedef struct {
 enum { ORC_TERM_RETURN = 1, ORC_TERM_RV = 2, ORC_TERMS_RSV = 3 };
 
 /* Random-number stream tags (Philox counter word 3). */
-enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1, ORC_TAG_THETA = 2, ORC_TAG_STEP = 3 };
+enum { ORC_TAG_MOMENTUM = 0, ORC_TAG_ACCEPT = 1, ORC_TAG_THETA = 2, ORC_TAG_STEP = 3,
+       ORC_TAG_MOVE = 4 };
+
+/* Moves that orc_run applies before each theta update (bit set). */
+enum { ORC_MOVE_LEVEL = 2 };
 
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
@@ -120,14 +124,33 @@ double orc_gamma(double alpha, uint64_t seed, uint64_t sweep, uint64_t chain, ui
 /* Compensated (Neumaier) sum. */
 double orc_neumaier_sum(int64_t n, const double *x);
 
+/* Level move of the whole state (an extension: the paper updates h only,
+ * and the Gibbs theta step alone moves slowly along this direction, on
+ * which ln RV pins xi + h_t):  h_t -> h_t + c, mu -> mu + c and, with the RV
+ * term, xi -> xi - c.  The AR(1) part and the RV residuals are unchanged, so
+ * along this orbit the posterior is the return term times the priors of mu
+ * and xi.  With the return term, e^{-c} is drawn from its exact law given
+ * the return term, Gamma(T/2, rate S/2) with S = sum y_t^2 e^{-h_t}, and the
+ * prior ratio of mu (and xi) decides a Metropolis test (an independence
+ * sampler along the orbit); without it, c is drawn from the Gaussian prior
+ * part.  Applied on h in place and *th.  Random
+ * numbers: stream tag 4, block 0 = (u0, u1 -> z by Box-Muller, u2 = test);
+ * Gamma attempts from block 1 on.  *c_out (may be NULL) receives the c
+ * applied (0 when rejected).  Returns a bit set: 2 = accepted, 4 = the Gamma
+ * draw ran out of attempts. */
+int orc_level_move(int64_t T, double *h, orc_theta *th, const double *y2, const orc_prior *pr,
+                   int terms, uint64_t seed, uint64_t sweep, uint64_t chain, double *c_out);
+
 /* n sweeps (trajectory, then optional theta update) of one chain; the step
- * size of each sweep is orc_step_size(seed, sweep, chain, dtau, jitter).
+ * size of each sweep is orc_step_size(seed, sweep, chain, dtau, jitter);
+ * with update_theta the moves `moves` (ORC_MOVE_LEVEL) run between the
+ * trajectory and the Gibbs theta update.
  * Traces (each may be NULL): dH[n], acc[n], theta[n] (after the sweep),
  * h_trace[n*T] (h after each sweep).  Returns the number accepted. */
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, double jitter, uint64_t seed, uint64_t chain,
-                uint64_t first_sweep, int64_t n_sweeps, int update_theta,
+                int32_t k, double dtau, double jitter, int moves, uint64_t seed,
+                uint64_t chain, uint64_t first_sweep, int64_t n_sweeps, int update_theta,
                 double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
                 double *h_trace);
 

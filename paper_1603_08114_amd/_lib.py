@@ -15,6 +15,7 @@ RSV_OK, RSV_EINVAL, RSV_EDEVICE, RSV_ENOMEM, RSV_ESTATE, RSV_ENONFINITE = 0, -1,
 RSV_F64, RSV_F32_MIXED = 0, 1
 RSV_TERM_RETURN, RSV_TERM_RV, RSV_TERMS_RSV = 1, 2, 3
 RSV_FLAG_NO_RESIDENT = 1
+RSV_FLAG_LEVEL_MOVE = 2
 
 THETA_KEYS = ("phi", "mu", "xi", "sig2_eta", "sig2_u")
 PRIOR_KEYS = ("mu_mean", "mu_var", "xi_mean", "xi_var",

@@ -89,7 +89,7 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_steps) {
 
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
-           edge = 0, accept = 0, counters = 0, total = 0;
+           edge = 0, accept = 0, shift = 0, counters = 0, total = 0;
     int32_t max_tiles = 0;
 };
 
@@ -113,6 +113,8 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
     if (!(pb->dtau_jitter >= 0.0 && pb->dtau_jitter < 1.0))
         return fail(RSV_EINVAL, "dtau_jitter must be in [0, 1)");
+    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE))
+        return fail(RSV_EINVAL, "unknown flags 0x%x", pb->flags);
     const rsv_prior& p = pb->prior;
     if (!(p.mu_var > 0 && p.xi_var > 0 && p.eta_shape > 0 && p.eta_scale > 0 && p.u_shape > 0 &&
           p.u_scale > 0 && std::isfinite(p.mu_mean) && std::isfinite(p.xi_mean) &&
@@ -169,6 +171,7 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->partials = take(tiles * kPart * sizeof(double));
     L->edge = take(n_chains * kEdge * sizeof(double));
     L->accept = take(n_chains * sizeof(int32_t));
+    L->shift = take(n_chains * sizeof(double));
     L->counters = take(kNumCounters * sizeof(uint32_t));
     L->total = off;
     L->max_tiles = static_cast<int32_t>(tiles);
@@ -198,6 +201,7 @@ struct rsv_ctx {
     double* partials = nullptr;
     double* edge = nullptr;
     int32_t* accept = nullptr;  // per chain: 1 if its current state is in h_prop
+    double* shift = nullptr;    // per chain: pending level shift of the current state
     uint32_t* counters = nullptr;
     // host mirrors of the current decomposition
     std::vector<rsv_leapfrog> lf;
@@ -217,6 +221,8 @@ struct rsv_ctx {
 };
 
 namespace {
+
+bool level_moves(const rsv_ctx* c) { return (c->pb.flags & RSV_FLAG_LEVEL_MOVE) != 0; }
 
 rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
     for (int s = 0; s < c->pb.n_series; ++s) {
@@ -312,6 +318,7 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.partials = c->partials;
     a.chain_edge = c->edge;
     a.jitter = c->pb.dtau_jitter;
+    a.shift = level_moves(c) ? c->shift : nullptr;
     a.terms = c->pb.terms;
     return a;
 }
@@ -349,6 +356,8 @@ FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do
     f.theta_trace = nullptr;
     f.stats_out = nullptr;
     f.counters = c->counters;
+    f.level_move = level_moves(c) ? 1 : 0;
+    f.shift = level_moves(c) ? c->shift : nullptr;
     return f;
 }
 
@@ -367,7 +376,8 @@ rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const do
     RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
     if (h_trace)
         RSV_HIP(launch_gather_state(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
-                                    c->h_prop, h_trace, c->pb.precision));
+                                    c->h_prop, level_moves(c) ? c->shift : nullptr, h_trace,
+                                    c->pb.precision));
     return RSV_OK;
 }
 
@@ -394,7 +404,7 @@ rsv_status run_resident(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps, int 
 // Leave every chain's current state in the caller's buffer.
 rsv_status settle(rsv_ctx* c) {
     RSV_HIP(launch_settle(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h, c->h_prop,
-                          c->pb.precision));
+                          level_moves(c) ? c->shift : nullptr, c->pb.precision));
     return RSV_OK;
 }
 
@@ -459,6 +469,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->partials = reinterpret_cast<double*>(c->ws + L.partials);
     c->edge = reinterpret_cast<double*>(c->ws + L.edge);
     c->accept = reinterpret_cast<int32_t*>(c->ws + L.accept);
+    c->shift = reinterpret_cast<double*>(c->ws + L.shift);
     c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
 
     auto bail = [&](rsv_status s) {
@@ -475,6 +486,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     RSV_HIP_INIT(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(uint32_t), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->edge, 0, c->n_chains * kEdge * sizeof(double), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->accept, 0, c->n_chains * sizeof(int32_t), c->stream));
+    RSV_HIP_INIT(hipMemsetAsync(c->shift, 0, c->n_chains * sizeof(double), c->stream));
     RSV_HIP_INIT(launch_prepare(c->stream, pb->y, pb->log_rv, c->n_data, c->y2_d, c->y2_f,
                                 c->lrv_f));
     RSV_HIP_INIT(launch_validate(c->stream, pb->y, pb->log_rv, c->n_data, h, c->n_state,
@@ -527,12 +539,12 @@ rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf
 rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
     RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
-                         c->h_prop, c->accept, c->pb.log_rv, c->partials, c->edge,
-                         c->pb.precision));
+                         c->h_prop, c->accept, level_moves(c) ? c->shift : nullptr, c->y2_d,
+                         c->pb.log_rv, c->partials, c->edge, c->pb.precision));
     FinalizeArgs f = finalize_args(c, sweep, 0, 1);
     f.stats_out = suff_stats;
     RSV_HIP(launch_finalize(c->stream, f, c->max_tiles_per_chain));
-    return RSV_OK;
+    return level_moves(c) ? settle(c) : RSV_OK;
 }
 
 rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
@@ -568,7 +580,8 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
                              ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
                              : nullptr;
             RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
-                                      c->h_prop, bs, trace->h_sq_sum, c->pb.precision));
+                                      c->h_prop, level_moves(c) ? c->shift : nullptr, bs,
+                                      trace->h_sq_sum, c->pb.precision));
         }
     }
     return settle(c);

@@ -15,7 +15,7 @@ namespace rsv {
 constexpr int kWave = 64;
 
 // Stream tags (word 3 of the Philox counter): one stream per use.
-enum : uint64_t { kTagMomentum = 0, kTagAccept = 1, kTagTheta = 2, kTagStep = 3 };
+enum : uint64_t { kTagMomentum = 0, kTagAccept = 1, kTagTheta = 2, kTagStep = 3, kTagMove = 4 };
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10: ten rounds; each round multiplies words 0 and 2 by the two

@@ -36,9 +36,11 @@ struct ChainDesc {
 };
 
 // Per-tile partial results (doubles): dH, then {B,B2,BB,D1,D2} of the
-// proposal h', then of the current h.  Padded to 16.
+// proposal h', then of the current h, then S = sum y_t^2 e^{-h_t} of h' and
+// of h (the level move's statistic).  Padded to 16.
 constexpr int kPart = 16;
-constexpr int kPartDH = 0, kPartProp = 1, kPartCur = 6;
+constexpr int kPartDH = 0, kPartProp = 1, kPartCur = 6, kPartSyProp = 11, kPartSyCur = 12;
+constexpr int kNQ = 13;  // partials in use
 // Per-chain edge values: b_first', b_last', b_first, b_last.
 constexpr int kEdge = 4;
 
@@ -67,6 +69,8 @@ struct TrajArgs {
     double* partials;           // kPart per tile
     double* chain_edge;         // kEdge per chain
     double jitter;              // step-size jitter j (0: fixed dtau)
+    const double* shift;        // per chain: pending level shift of the current
+                                // state (value = stored + shift), or nullptr
     int32_t terms;
 };
 
@@ -89,6 +93,8 @@ struct FinalizeArgs {
     rsv_theta* theta_trace;     // per chain or nullptr
     double* stats_out;          // 7 per chain or nullptr
     uint32_t* counters;
+    int32_t level_move;         // apply the level move before the Gibbs theta step
+    double* shift;              // per chain pending level shift (with level_move)
 };
 
 // Record the message returned by rsv_last_error() and return `code`.
@@ -125,18 +131,22 @@ hipError_t launch_resident(hipStream_t st, int precision, int S, bool mass, cons
 // Copy every chain's current state (selected by state_sel) into h_dst.
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,
-                               const void* h_b, void* h_dst, int precision);
+                               const void* h_b, const double* shift, void* h_dst, int precision);
 // Add every chain's current state to batch_sum (and its square to sq_sum).
 hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                              int32_t max_T, const int32_t* state_sel, const void* h_a,
-                             const void* h_b, double* batch_sum, double* sq_sum, int precision);
-// Move chains whose current state is in h_b back into h_a and clear state_sel.
+                             const void* h_b, const double* shift, double* batch_sum,
+                             double* sq_sum, int precision);
+// Leave every chain's current state (including a pending level shift) in h_a;
+// clear state_sel and the shifts.
 hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
-                         int32_t* state_sel, void* h_a, const void* h_b, int precision);
+                         int32_t* state_sel, void* h_a, const void* h_b, double* shift,
+                         int precision);
 hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
                         const ChainDesc* chains, const rsv_theta* theta, const void* h_a,
-                        const void* h_b, const int32_t* state_sel, const double* lrv_d,
-                        double* partials, double* chain_edge, int precision);
+                        const void* h_b, const int32_t* state_sel, const double* shift,
+                        const double* y2_d, const double* lrv_d, double* partials,
+                        double* chain_edge, int precision);
 hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                           int32_t max_T, const float* log_mass, uint64_t seed, uint64_t sweep,
                           double* p_out);

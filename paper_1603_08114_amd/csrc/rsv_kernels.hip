@@ -30,6 +30,14 @@ __device__ inline double exp_neg<double>(double x) { return exp_force(-x); }
 template <>
 __device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
 
+// Value of the current state at a site: the stored entry plus the chain's
+// pending level shift (0 unless level moves are on), rounded to the state's
+// precision.  Every reader of the current state goes through this.
+template <typename R>
+__device__ __forceinline__ R state_at(const R* hc, int64_t t, double shift) {
+    return static_cast<R>(static_cast<double>(hc[t]) + shift);
+}
+
 // Step size of one trajectory: dtau scaled by 1 + j (2u - 1), u the first
 // uniform of block 0 of the step stream (every tile of a chain draws the same
 // u).  Rounded step by step, without contraction, so the value is exact to
@@ -57,7 +65,7 @@ template <typename R, int NW>
 struct TileShared {
     R left[2][NW];   // h of the first site of each wavefront
     R right[2][NW];  // h of the last site of each wavefront
-    double red[NW][11];
+    double red[NW][kNQ];
     double up1[NW], up0[NW];
 };
 
@@ -88,6 +96,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 
     const bool in_b = A.state_sel[td.chain] != 0;
     const R* hc = (in_b ? A.h_b : A.h_a) + cd.h_off;
+    const double shift = A.shift ? A.shift[td.chain] : 0.0;
     R* hp = (in_b ? const_cast<R*>(A.h_a) : A.h_b) + cd.h_off;
     const R* y2 = A.y2 + cd.d_off;
     const R* lr = A.lrv + cd.d_off;
@@ -95,7 +104,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         const bool live = t < T;
-        h[j] = live ? hc[t] : R(0);
+        h[j] = live ? state_at(hc, t, shift) : R(0);
         const double yy = live ? static_cast<double>(y2[t]) : 0.0;
         const double rr = live ? static_cast<double>(lr[t]) : 0.0;
         dc[j] = static_cast<R>(-dt * (c_base - rr * inv_su));
@@ -200,7 +209,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
-        h0d[j] = (t < T) ? static_cast<double>(hc[t]) : 0.0;
+        h0d[j] = (t < T) ? static_cast<double>(state_at(hc, t, shift)) : 0.0;
     }
     double h1_up = static_cast<double>(from_upper(h[0]));
     double h0_up = from_upper(h0d[0]);
@@ -218,6 +227,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 
     double dH = -kin0;
     double s1[5] = {0, 0, 0, 0, 0}, s0[5] = {0, 0, 0, 0, 0};
+    double sy1 = 0.0, sy0 = 0.0;  // sum y^2 e^{-h} of h' and h
     double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
@@ -229,7 +239,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const double im = MASS ? exp_fast(-static_cast<double>(lm[t])) : 1.0;
         const double rr = lrd[t];
         double d = 0.5 * pj * pj * im;
-        if (RET) d += 0.5 * (h1 - h0) + 0.5 * y2d[t] * exp_fast(-h0) * expm1_abs(h0 - h1);
+        if (RET) {
+            const double ye0 = y2d[t] * exp_fast(-h0);
+            const double x10 = exp_fast(h0 - h1);  // e^{-h1} / e^{-h0}
+            d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
+            sy1 += ye0 * x10;
+            sy0 += ye0;
+        }
         if (rv) {
             const double c = rr - xi;
             const double e1 = c - h1, e0 = c - h0;
@@ -261,8 +277,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         hp[t] = h[j];
     }
 
-    double red[11];
+    double red[kNQ];
     red[kPartDH] = wave_sum(dH);
+    red[kPartSyProp] = wave_sum(sy1);
+    red[kPartSyCur] = wave_sum(sy0);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         red[kPartProp + q] = wave_sum(s1[q]);
@@ -271,12 +289,12 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     if constexpr (NW > 1) {
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < 11; ++q) sh.red[wv][q] = red[q];
+            for (int q = 0; q < kNQ; ++q) sh.red[wv][q] = red[q];
         }
         __syncthreads();
         if (wv == 0) {
 #pragma unroll
-            for (int q = 0; q < 11; ++q) {
+            for (int q = 0; q < kNQ; ++q) {
                 double v = sh.red[0][q];
                 for (int x = 1; x < NW; ++x) v += sh.red[x][q];
                 red[q] = v;
@@ -286,7 +304,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     if (wv == 0 && lane == 0) {
         double* out = A.partials + static_cast<int64_t>(tile_id) * kPart;
 #pragma unroll
-        for (int q = 0; q < 11; ++q) out[q] = red[q];
+        for (int q = 0; q < kNQ; ++q) out[q] = red[q];
     }
 }
 
@@ -330,7 +348,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_tiles,
                                                const ChainDesc* chains, const rsv_theta* theta,
                                                const R* h_a, const R* h_b,
-                                               const int32_t* state_sel, const double* lrv_d,
+                                               const int32_t* state_sel, const double* shift,
+                                               const double* y2_d, const double* lrv_d,
                                                double* partials, double* chain_edge) {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -339,24 +358,29 @@ __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_
     const ChainDesc cd = chains[td.chain];
     const rsv_theta th = theta[td.chain];
     const R* hc = (state_sel[td.chain] ? h_b : h_a) + cd.h_off;
+    const double sft = shift ? shift[td.chain] : 0.0;
     const double* lr = lrv_d + cd.d_off;
-    double s[5] = {0, 0, 0, 0, 0};
+    const double* yy = y2_d + cd.d_off;
+    double s[6] = {0, 0, 0, 0, 0, 0};
     for (int t = td.a + lane; t < td.b; t += kWave) {
-        const double b = static_cast<double>(hc[t]) - th.mu;
-        const double e = lr[t] - static_cast<double>(hc[t]) - th.xi;
+        const double hv = static_cast<double>(state_at(hc, t, sft));
+        const double b = hv - th.mu;
+        const double e = lr[t] - hv - th.xi;
         s[0] += b;
         s[1] += b * b;
-        if (t + 1 < cd.T) s[2] += b * (static_cast<double>(hc[t + 1]) - th.mu);
+        if (t + 1 < cd.T) s[2] += b * (static_cast<double>(state_at(hc, t + 1, sft)) - th.mu);
         s[3] += e;
         s[4] += e * e;
+        s[5] += yy[t] * exp_fast(-hv);
         if (t == 0) chain_edge[static_cast<int64_t>(td.chain) * kEdge + 2] = b;
         if (t == cd.T - 1) chain_edge[static_cast<int64_t>(td.chain) * kEdge + 3] = b;
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) s[q] = wave_sum(s[q]);
+    for (int q = 0; q < 6; ++q) s[q] = wave_sum(s[q]);
     if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) partials[static_cast<int64_t>(w) * kPart + kPartCur + q] = s[q];
+        partials[static_cast<int64_t>(w) * kPart + kPartSyCur] = s[5];
     }
 }
 
@@ -368,26 +392,59 @@ __global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_
 // first accepted attempt is the draw).  None of these depends on the other
 // parameters except through the known Gamma shapes a + T/2, so one lane per
 // block evaluates them all in parallel; one lane then does the algebra.
+// The level move draws from its own stream (tag 4): block 0 (z_c, u_c) and
+// the Gamma(T/2) attempts in blocks 1..32; they follow the theta blocks and
+// the Metropolis uniform in the draw index.
 // ---------------------------------------------------------------------------
 constexpr int kGammaTries = 32;
 constexpr int kGammaEtaBlock = 2, kGammaUBlock = 2 + kGammaTries;
 constexpr int kThetaBlocks = 2 + 2 * kGammaTries;
+constexpr int kAcceptBlock = kThetaBlocks;
+constexpr int kMoveBlock = kThetaBlocks + 1;            // block 0 of the move stream
+constexpr int kMoveGammaBlock = kMoveBlock + 1;         // its Gamma attempts
+constexpr int kDrawBlocks = kMoveGammaBlock + kGammaTries;
 
 struct ThetaDraws {
-    double z_mu, z_phi, u_phi, z_xi, log_u_accept;
-    double g_val[kThetaBlocks];   // d v^3 of each Gamma attempt
-    int g_ok[kThetaBlocks];       // attempt accepted
+    double z_mu, z_phi, u_phi, z_xi, log_u_accept, z_c, u_c;
+    double g_val[kDrawBlocks];    // d v^3 of each Gamma attempt
+    int g_ok[kDrawBlocks];        // attempt accepted
 };
 
-// Block b of the theta stream (or, for b == kThetaBlocks, the Metropolis
-// uniform) for chain c.
+__device__ void gamma_attempt(int b, ThetaDraws& D, const double u[4], double z0, double shape) {
+#pragma clang fp contract(off)
+    const double d = shape - 1.0 / 3.0;
+    const double cc = 1.0 / sqrt(9.0 * d);
+    double v = 1.0 + cc * z0;
+    int ok = 0;
+    if (v > 0.0) {
+        v = v * v * v;
+        ok = log(u[2]) < 0.5 * z0 * z0 + d - d * v + d * log(v);
+    }
+    D.g_ok[b] = ok;
+    D.g_val[b] = ok ? d * v : d;
+}
+
+// Draw block b for chain c: theta stream blocks, the Metropolis uniform, the
+// level move's blocks.
 __device__ void theta_draw_block(int b, ThetaDraws& D, uint64_t seed, uint64_t sweep, uint64_t c,
-                                 double shape_eta, double shape_u) {
+                                 double shape_eta, double shape_u, double shape_level) {
 #pragma clang fp contract(off)
     double u[4];
-    if (b == kThetaBlocks) {
+    if (b == kAcceptBlock) {
         uniforms4(seed, 0, sweep, c, kTagAccept, u);
         D.log_u_accept = log(u[0]);
+        return;
+    }
+    if (b >= kMoveBlock) {
+        uniforms4(seed, static_cast<uint64_t>(b - kMoveBlock), sweep, c, kTagMove, u);
+        double z0, z1;
+        gauss_pair(u[0], u[1], z0, z1);
+        if (b == kMoveBlock) {
+            D.z_c = z0;
+            D.u_c = u[2];
+        } else {
+            gamma_attempt(b, D, u, z0, shape_level);
+        }
         return;
     }
     uniforms4(seed, static_cast<uint64_t>(b), sweep, c, kTagTheta, u);
@@ -400,17 +457,7 @@ __device__ void theta_draw_block(int b, ThetaDraws& D, uint64_t seed, uint64_t s
     } else if (b == 1) {
         D.z_xi = z0;
     } else {
-        const double shape = b < kGammaUBlock ? shape_eta : shape_u;
-        const double d = shape - 1.0 / 3.0;
-        const double cc = 1.0 / sqrt(9.0 * d);
-        double v = 1.0 + cc * z0;
-        int ok = 0;
-        if (v > 0.0) {
-            v = v * v * v;
-            ok = log(u[2]) < 0.5 * z0 * z0 + d - d * v + d * log(v);
-        }
-        D.g_ok[b] = ok;
-        D.g_val[b] = ok ? d * v : d;
+        gamma_attempt(b, D, u, z0, b < kGammaUBlock ? shape_eta : shape_u);
     }
 }
 
@@ -420,6 +467,41 @@ __device__ double first_gamma(const ThetaDraws& D, int first, bool& ran_out) {
     ran_out = true;
     return D.g_val[first];  // d, the attempt's fallback
 }
+
+// Level move along h -> h + c, mu -> mu + c (xi -> xi - c with the RV term):
+// the return term gives e^{-c} ~ Gamma(T/2, rate S/2) with S = sum y^2 e^{-h},
+// and the prior ratio of mu (and xi) is the Metropolis test; without the
+// return term c is drawn from the Gaussian prior factors.  Returns the c
+// applied (0 when rejected) and moves cur.mu / cur.xi.
+__device__ double level_move(rsv_theta& cur, double S, const rsv_prior& pr, int terms,
+                             const ThetaDraws& D, bool& ran_out) {
+#pragma clang fp contract(off)
+    const bool rv = (terms & RSV_TERM_RV) != 0;
+    double c;
+    bool accept;
+    if (terms & RSV_TERM_RETURN) {
+        const double g = first_gamma(D, kMoveGammaBlock, ran_out);
+        c = -log(2.0 * g / S);
+        const double dm0 = cur.mu - pr.mu_mean, dm1 = cur.mu + c - pr.mu_mean;
+        double log_a = -0.5 * dm1 * dm1 / pr.mu_var - (-0.5 * dm0 * dm0 / pr.mu_var);
+        if (rv) {
+            const double dx0 = cur.xi - pr.xi_mean, dx1 = cur.xi - c - pr.xi_mean;
+            log_a += -0.5 * dx1 * dx1 / pr.xi_var - (-0.5 * dx0 * dx0 / pr.xi_var);
+        }
+        accept = isfinite(c) && log(D.u_c) < log_a;
+    } else {
+        const double prec = 1.0 / pr.mu_var + (rv ? 1.0 / pr.xi_var : 0.0);
+        const double lin = (pr.mu_mean - cur.mu) / pr.mu_var
+                         + (rv ? (cur.xi - pr.xi_mean) / pr.xi_var : 0.0);
+        c = lin / prec + D.z_c / sqrt(prec);
+        accept = true;
+    }
+    if (!accept) return 0.0;
+    cur.mu += c;
+    if (rv) cur.xi -= c;
+    return c;
+}
+
 
 __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
                                  const rsv_prior& pr, int terms, const ThetaDraws& D,
@@ -472,7 +554,6 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
 // Per-chain finalize: reduce tile partials (compensated, fixed order), the
 // Metropolis test, the choice of statistics, and the theta update.
 // ---------------------------------------------------------------------------
-constexpr int kNQ = 11;
 
 // Everything the finalize does for chain c, by the NT threads of a block
 // (shared scratch passed in); returns in every thread.
@@ -486,14 +567,19 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
     const int wv = tid / kWave;
     const ChainDesc cd = A.chains[c];
 
-    // random numbers of this chain's Metropolis test and theta update
+    // random numbers of this chain's Metropolis test, level move and theta update
     {
         const double n = static_cast<double>(cd.T);
-        const int first = A.do_theta ? 0 : kThetaBlocks;
-        const int last = (A.do_metropolis && !A.log_u) ? kThetaBlocks : kThetaBlocks - 1;
-        for (int b = first + tid; b <= last; b += NT)
-            theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
-                             A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n);
+        const bool need_theta = A.do_theta != 0;
+        const bool need_accept = A.do_metropolis && !A.log_u;
+        const bool need_move = A.do_theta && A.level_move;
+        for (int b = tid; b < kDrawBlocks; b += NT) {
+            const bool need = b < kThetaBlocks ? need_theta
+                                               : (b == kAcceptBlock ? need_accept : need_move);
+            if (need)
+                theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+        }
     }
 
     Comp acc[NQ];
@@ -550,12 +636,21 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         for (int q = 0; q < 7; ++q) A.stats_out[static_cast<int64_t>(c) * 7 + q] = st[q];
     }
     rsv_theta out = th;
+    // the pending level shift belongs to the buffer that held the current state
+    double shift = (A.shift && !use_prop) ? A.shift[c] : 0.0;
     if (A.do_theta) {
         bool ran_out = false;
-        out = gibbs_theta(st, static_cast<double>(cd.T), th, A.prior, A.terms, draws, ran_out);
+        rsv_theta cur = th;
+        if (A.level_move) {
+            // h - mu and r - xi - h are unchanged by the move, so the statistics are too
+            const double S = tot[use_prop ? kPartSyProp : kPartSyCur];
+            shift += level_move(cur, S, A.prior, A.terms, draws, ran_out);
+        }
+        out = gibbs_theta(st, static_cast<double>(cd.T), cur, A.prior, A.terms, draws, ran_out);
         if (ran_out) atomicAdd(&A.counters[kCntGammaExhausted], 1u);
         A.theta[c] = out;
     }
+    if (A.shift) A.shift[c] = shift;
     if (A.theta_trace) A.theta_trace[c] = out;
 }
 
@@ -601,6 +696,7 @@ __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
         __syncthreads();
         if (RA.h_trace || RA.batch_sum || RA.sq_sum) {
             const R* src = (RA.traj.state_sel[c] ? RA.traj.h_b : RA.traj.h_a) + cd.h_off;
+            const double sft = RA.fin.shift ? RA.fin.shift[c] : 0.0;
             R* ht = RA.h_trace ? RA.h_trace + static_cast<int64_t>(i) * RA.n_state + cd.h_off
                                : nullptr;
             double* bs = RA.batch_sum
@@ -608,7 +704,7 @@ __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
                              : nullptr;
             double* sq = RA.sq_sum ? RA.sq_sum + cd.h_off : nullptr;
             for (int t = threadIdx.x; t < cd.T; t += blockDim.x) {
-                const R v = src[t];
+                const R v = state_at(src, t, sft);
                 if (ht) ht[t] = v;
                 const double vd = static_cast<double>(v);
                 if (bs) bs[t] += vd;
@@ -625,49 +721,60 @@ __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather_state(const ChainDesc* chains,
                                                       const int32_t* state_sel, const R* h_a,
-                                                      const R* h_b, R* h_dst) {
+                                                      const R* h_b, const double* shift,
+                                                      R* h_dst) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
-    const R* src = state_sel[c] ? h_b : h_a;
+    const R* src = (state_sel[c] ? h_b : h_a) + cd.h_off;
+    const double sft = shift ? shift[c] : 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
          t += stride)
-        h_dst[cd.h_off + t] = src[cd.h_off + t];
+        h_dst[cd.h_off + t] = state_at(src, t, sft);
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_accumulate(const ChainDesc* chains,
                                                     const int32_t* state_sel, const R* h_a,
-                                                    const R* h_b, double* batch_sum,
-                                                    double* sq_sum) {
+                                                    const R* h_b, const double* shift,
+                                                    double* batch_sum, double* sq_sum) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
-    const R* src = state_sel[c] ? h_b : h_a;
+    const R* src = (state_sel[c] ? h_b : h_a) + cd.h_off;
+    const double sft = shift ? shift[c] : 0.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
          t += stride) {
         const int64_t i = cd.h_off + t;
-        const double v = static_cast<double>(src[i]);
+        const double v = static_cast<double>(state_at(src, t, sft));
         if (batch_sum) batch_sum[i] += v;
         if (sq_sum) sq_sum[i] += v * v;
     }
 }
 
+// Writes the current state (buffer h_b when selected, plus the pending shift)
+// into h_a.  Chains already in h_a with no shift are left alone.
 template <typename R>
 __global__ __launch_bounds__(256) void k_settle(const ChainDesc* chains, const int32_t* state_sel,
-                                                R* h_a, const R* h_b) {
+                                                R* h_a, const R* h_b, const double* shift) {
     const int c = blockIdx.y;
-    if (!state_sel[c]) return;
+    const double sft = shift ? shift[c] : 0.0;
+    if (!state_sel[c] && sft == 0.0) return;
     const ChainDesc cd = chains[c];
+    const R* src = (state_sel[c] ? h_b : h_a) + cd.h_off;
+    R* dst = h_a + cd.h_off;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
          t += stride)
-        h_a[cd.h_off + t] = h_b[cd.h_off + t];
+        dst[t] = state_at(src, t, sft);
 }
 
-__global__ void k_clear_sel(int32_t* state_sel, int32_t n) {
+__global__ void k_clear_sel(int32_t* state_sel, double* shift, int32_t n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) state_sel[i] = 0;
+    if (i < n) {
+        state_sel[i] = 0;
+        if (shift) shift[i] = 0.0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -847,61 +954,64 @@ hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_ti
 
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,
-                               const void* h_b, void* h_dst, int precision) {
+                               const void* h_b, const double* shift, void* h_dst, int precision) {
     const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_gather_state<double>, g, b, 0, st, chains, state_sel,
                            static_cast<const double*>(h_a), static_cast<const double*>(h_b),
-                           static_cast<double*>(h_dst));
+                           shift, static_cast<double*>(h_dst));
     else
         hipLaunchKernelGGL(k_gather_state<float>, g, b, 0, st, chains, state_sel,
                            static_cast<const float*>(h_a), static_cast<const float*>(h_b),
-                           static_cast<float*>(h_dst));
+                           shift, static_cast<float*>(h_dst));
     return hipGetLastError();
 }
 
 hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                              int32_t max_T, const int32_t* state_sel, const void* h_a,
-                             const void* h_b, double* batch_sum, double* sq_sum, int precision) {
+                             const void* h_b, const double* shift, double* batch_sum,
+                             double* sq_sum, int precision) {
     const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_accumulate<double>, g, b, 0, st, chains, state_sel,
                            static_cast<const double*>(h_a), static_cast<const double*>(h_b),
-                           batch_sum, sq_sum);
+                           shift, batch_sum, sq_sum);
     else
         hipLaunchKernelGGL(k_accumulate<float>, g, b, 0, st, chains, state_sel,
                            static_cast<const float*>(h_a), static_cast<const float*>(h_b),
-                           batch_sum, sq_sum);
+                           shift, batch_sum, sq_sum);
     return hipGetLastError();
 }
 
 hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,
-                         int32_t* state_sel, void* h_a, const void* h_b, int precision) {
+                         int32_t* state_sel, void* h_a, const void* h_b, double* shift,
+                         int precision) {
     const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_settle<double>, g, b, 0, st, chains, state_sel,
-                           static_cast<double*>(h_a), static_cast<const double*>(h_b));
+                           static_cast<double*>(h_a), static_cast<const double*>(h_b), shift);
     else
         hipLaunchKernelGGL(k_settle<float>, g, b, 0, st, chains, state_sel,
-                           static_cast<float*>(h_a), static_cast<const float*>(h_b));
+                           static_cast<float*>(h_a), static_cast<const float*>(h_b), shift);
     hipLaunchKernelGGL(k_clear_sel, dim3((n_chains + 255) / 256), dim3(256), 0, st, state_sel,
-                       n_chains);
+                       shift, n_chains);
     return hipGetLastError();
 }
 
 hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
                         const ChainDesc* chains, const rsv_theta* theta, const void* h_a,
-                        const void* h_b, const int32_t* state_sel, const double* lrv_d,
-                        double* partials, double* chain_edge, int precision) {
+                        const void* h_b, const int32_t* state_sel, const double* shift,
+                        const double* y2_d, const double* lrv_d, double* partials,
+                        double* chain_edge, int precision) {
     const dim3 g((n_tiles + 3) / 4), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_stats<double>, g, b, 0, st, tiles, n_tiles, chains, theta,
                            static_cast<const double*>(h_a), static_cast<const double*>(h_b),
-                           state_sel, lrv_d, partials, chain_edge);
+                           state_sel, shift, y2_d, lrv_d, partials, chain_edge);
     else
         hipLaunchKernelGGL(k_stats<float>, g, b, 0, st, tiles, n_tiles, chains, theta,
                            static_cast<const float*>(h_a), static_cast<const float*>(h_b),
-                           state_sel, lrv_d, partials, chain_edge);
+                           state_sel, shift, y2_d, lrv_d, partials, chain_edge);
     return hipGetLastError();
 }
 

@@ -69,6 +69,7 @@ def test_workspace_and_state_sizes():
     dict(offsets=[0, 100], waves_per_tile=3),
     dict(offsets=[0, 100], dtau_jitter=1.0),
     dict(offsets=[0, 100], dtau_jitter=-0.1),
+    dict(offsets=[0, 100], flags=8),
     dict(offsets=[0, 100], prior=dict(mu_var=-1.0)),
 ])
 def test_invalid_problems_rejected_on_host(bad):

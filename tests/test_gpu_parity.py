@@ -42,14 +42,14 @@ def state_from(hs, C, jitter=0.0, seed=0):
 
 
 def sampler(Ts, C=1, seed=5, k=20, precision=RSV_F64, thetas=None, log_mass=None, S=0,
-            terms=3, jitter=0.05, NW=0, dtau_jitter=0.0):
+            terms=3, jitter=0.05, NW=0, dtau_jitter=0.0, flags=0):
     offsets, ys, rs, hs = make_series(Ts, 100 + seed, thetas)
     h0 = state_from(hs, C, jitter)
     th = [thetas[s] if thetas else TH for s in range(len(Ts)) for _ in range(C)]
     smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                          chains_per_series=C, precision=precision, max_steps=k, seed=seed,
                          log_mass=log_mass, sites_per_lane=S, waves_per_tile=NW, terms=terms,
-                         dtau_jitter=dtau_jitter)
+                         dtau_jitter=dtau_jitter, flags=flags)
     return smp, offsets, ys, rs, h0, th
 
 
@@ -223,6 +223,51 @@ def test_sweep_with_step_jitter_matches_oracle():
             assert rel_inf(smp.h.cpu().numpy()[sl], ref["h"]) <= 1e-10
 
 
+@pytest.mark.parametrize("terms", [3, 1, 2])
+def test_sweep_with_level_move_matches_oracle(terms):
+    """Level move before every theta update (ragged chains over several tiles,
+    two chains per series, jittered step): accept sequence, dH and theta
+    against the oracle's chain with the same move; h at the end."""
+    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
+    Ts, C, k, dt, n, j = [700, 2600], 2, 20, 0.04, 40, 0.3
+    thetas = synth.draw_batch_thetas(len(Ts), 8)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, thetas=thetas, dtau_jitter=j,
+                                           terms=terms, flags=RSV_FLAG_LEVEL_MOVE)
+    out = smp.sweep(30, n, (k, dt), update_theta=True)
+    acc = out["accepted"].cpu().numpy()
+    dh = out["delta_h"].cpu().numpy()
+    tht = out["theta"].cpu().numpy()
+    h_end = smp.h.cpu().numpy()
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        ref = oracle.run(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, seed=smp.pb.seed,
+                         chain=c, first_sweep=30, jitter=j, moves=oracle.MOVE_LEVEL, terms=terms)
+        m = _compare_runs(acc[:, c], dh[:, c], tht[:, c], ref, smp.pb.seed, c, 30)
+        if m == n:
+            assert rel_inf(h_end[sl], ref["h"]) <= 1e-10
+        # the move did move the level: mu changes on (almost) every sweep
+        assert np.mean(np.diff(tht[:, c, 1]) != 0) > 0.9
+
+
+def test_theta_update_with_level_move_matches_oracle():
+    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
+    Ts, C = [1500, 5000], 2
+    thetas = synth.draw_batch_thetas(len(Ts), 3)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, thetas=thetas, flags=RSV_FLAG_LEVEL_MOVE)
+    st = smp.theta_update(sweep=4).cpu().numpy()
+    th_gpu = smp.theta.cpu().numpy()
+    h_gpu = smp.h.cpu().numpy()
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        mv = oracle.level_move(h0[sl], th[c], ys[s] ** 2, smp.pb.seed, 4, c)
+        assert mv["flags"] & 2
+        ref_st = oracle.suffstats(mv["h"], rs[s], mv["theta"]["mu"], mv["theta"]["xi"])
+        np.testing.assert_allclose(st[c], ref_st, rtol=1e-10, atol=1e-10 * np.abs(ref_st).max())
+        ref_th, _ = oracle.theta_update(sl.stop - sl.start, ref_st, mv["theta"], smp.pb.seed, 4, c)
+        got = dict(zip(oracle.THETA_KEYS, th_gpu[c]))
+        for key in oracle.THETA_KEYS:
+            assert got[key] == pytest.approx(ref_th[key], rel=1e-10, abs=1e-13), (c, key)
+        assert rel_inf(h_gpu[sl], mv["h"]) <= 1e-13
+
+
 def test_linear_gaussian_terms_f64():
     k, dt = 20, 0.05
     smp, offsets, ys, rs, h0, th = sampler([1000], 1, k=k, terms=RSV_TERM_RV)
@@ -371,9 +416,9 @@ def test_batch_mean_accumulators_match_recorded_trace():
     np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq, rtol=1e-14)
 
 
-@pytest.mark.parametrize("precision,dtau_jitter", [(RSV_F64, 0.0), (RSV_F32_MIXED, 0.0),
-                                                   (RSV_F64, 0.3)])
-def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter):
+@pytest.mark.parametrize("precision,dtau_jitter,flags", [(RSV_F64, 0.0, 0), (RSV_F32_MIXED, 0.0, 0),
+                                                         (RSV_F64, 0.3, 2), (RSV_F32_MIXED, 0.3, 2)])
+def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter, flags):
     """Chains that fit one tile run all sweeps in one launch; the result must
     be bitwise the one of one launch per kernel per sweep."""
     from paper_1603_08114_amd._lib import RSV_FLAG_NO_RESIDENT
@@ -383,10 +428,10 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter):
     h0 = state_from(hs, C, 0.02)
     th = [thetas[s] for s in range(len(Ts)) for _ in range(C)]
     outs = []
-    for flags in (0, RSV_FLAG_NO_RESIDENT):
+    for path in (0, RSV_FLAG_NO_RESIDENT):
         smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                              chains_per_series=C, precision=precision, max_steps=k, seed=4,
-                             flags=flags, dtau_jitter=dtau_jitter)
+                             flags=flags | path, dtau_jitter=dtau_jitter)
         o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True, batch_len=7)
         o["state"] = smp.h.clone()
         o["theta_final"] = smp.theta.clone()
