@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--sites-per-lane", type=int, default=8)
     ap.add_argument("--waves-per-tile", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--level-move", type=int, default=-1, choices=[-1, 0, 1],
+                    help="level move of (h, mu, xi) before each theta update; -1 = the "
+                         "workload's default (off for long and small, on for batched and mass)")
     ap.add_argument("--dtau-jitter", type=float, default=-1.0,
                     help="step-size jitter j (dtau * U[1-j, 1+j] per trajectory); -1 = the "
                          "workload's default (0 for the fixed-dtau long and small workloads, "
@@ -176,17 +179,19 @@ def min_ess_from_traces(h_trace, theta_trace):
     return float(min(np.nanmin(ess_h), np.nanmin(ess_th))), ess_h, ess_th
 
 
-def run_small(args):
-    """Single series, T = 1000, k = 20, dtau = 0.05, 500 burn-in + 5000 sweeps,
-    theta every sweep, FP64: min over {h_t} and theta of the ESS per second."""
+def small_chain(jit, level, with_oracle):
+    """The single-series run (T = 1000, k = 20, dtau = 0.05, 500 burn-in +
+    5000 sweeps, theta every sweep, FP64) on the GPU and, optionally, the same
+    chain on the oracle.  Returns (GPU record, oracle record or None)."""
     import torch
     import synth
     from paper_1603_08114_amd import api
+    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
     T, k, dtau, burn, n = 1000, 20, 0.05, 500, 5000
-    jit = jitter_of(args, 0.0)
     theta = dict(synth.THETA_STAR)
     y, lr, h_true = synth.simulate_rsv(T, theta, 1)
-    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1, dtau_jitter=jit)
+    smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1, dtau_jitter=jit,
+                         flags=RSV_FLAG_LEVEL_MOVE if level else 0)
     smp.sweep(0, burn, (k, dtau), update_theta=True, record=())
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -199,32 +204,59 @@ def run_small(args):
     elapsed = ev0.elapsed_time(ev1) / 1e3
     min_ess, ess_h, ess_th = min_ess_from_traces(out["h"].cpu().numpy(),
                                                  out["theta"][:, 0].cpu().numpy())
-    res = {"metric": METRIC, "value": min_ess / elapsed, "unit": "min-ESS/s", "n_gpus": 1,
-           "steps": n, "warmup": burn, "ms_per_step": elapsed / n * 1e3,
+    gpu = {"min_ess_per_s": min_ess / elapsed, "seconds": elapsed, "min_ess": min_ess,
+           "min_ess_h": float(np.min(ess_h)),
+           "min_ess_theta": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
+                                     map(float, ess_th))),
+           "acceptance": float(out["accepted"].float().mean().item()),
+           "site_updates_per_s": T * k * n / elapsed}
+    smp.close()
+    ref = None
+    if with_oracle:
+        import time as _t
+        import oracle
+        t0 = _t.perf_counter()
+        r = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True,
+                       jitter=jit, moves=oracle.MOVE_LEVEL if level else 0)
+        dt = _t.perf_counter() - t0
+        m_ref, _, _ = min_ess_from_traces(r["h_trace"][burn:], r["theta_trace"][burn:])
+        ref = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "the whole run (500 + 5000 sweeps), serial C; time pro-rated to the "
+                         "5000 measured sweeps",
+               "site_updates_per_s": T * k * (burn + n) / dt, "seconds": dt, "min_ess": m_ref}
+    return gpu, ref
+
+
+def run_small(args):
+    """Single series, T = 1000, k = 20, dtau = 0.05, 500 burn-in + 5000 sweeps,
+    theta every sweep, FP64: min over {h_t} and theta of the ESS per second.
+    value: the paper's sampler (fixed dtau, Gibbs theta); beside it the same
+    workload with step-size jitter 0.5 and the level move."""
+    jit = jitter_of(args, 0.0)
+    level = level_of(args, False)
+    gpu, ref = small_chain(jit, level, args.cpu_sweeps > 0)
+    res = {"metric": METRIC, "value": gpu["min_ess_per_s"], "unit": "min-ESS/s", "n_gpus": 1,
+           "steps": 5000, "warmup": 500, "ms_per_step": gpu["seconds"] / 5000 * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": "single-series RSV HMC, T=1000, k=20, dtau=0.05, FP64, "
                                   "500 burn-in + 5000 sweeps, theta every sweep"
-                                  + (f", dtau jitter {jit}" if jit else ""),
-                      "T": T, "k": k, "dtau": dtau, "dtau_jitter": jit, "chains": 1},
-           "site_updates_per_s": T * k * n / elapsed, "min_ess": min_ess,
-           "min_ess_theta": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
-                                     map(float, ess_th))),
-           "acceptance": float(out["accepted"].float().mean().item())}
-    if args.cpu_sweeps > 0:
-        import time as _t
-        import oracle
-        t0 = _t.perf_counter()
-        ref = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True,
-                         jitter=jit)
-        dt = _t.perf_counter() - t0
-        m_ref, _, _ = min_ess_from_traces(ref["h_trace"][burn:], ref["theta_trace"][burn:])
-        res["cpu_baseline"] = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "the whole run (500 + 5000 sweeps), serial C; time "
-                                         "pro-rated to the 5000 measured sweeps",
-                               "site_updates_per_s": T * k * (burn + n) / dt, "seconds": dt}
+                                  + (f", dtau jitter {jit}" if jit else "")
+                                  + (", level move" if level else ""),
+                      "T": 1000, "k": 20, "dtau": 0.05, "dtau_jitter": jit,
+                      "level_move": bool(level), "chains": 1}}
+    res.update({k_: v for k_, v in gpu.items() if k_ not in ("min_ess_per_s", "seconds")})
+    if ref:
+        res["cpu_baseline"] = ref
+    if not jit and not level:
+        g2, r2 = small_chain(0.5, True, args.cpu_sweeps > 0)
+        res["with_jitter_and_level_move"] = {"gpu": g2, "oracle": r2}
     return res
+
+
+def level_of(args, default):
+    return default if args.level_move < 0 else bool(args.level_move)
 
 
 def jitter_of(args, default):
@@ -248,9 +280,18 @@ def run_batched(args):
     h0 = np.concatenate([np.tile(data["h_true"][off[s]:off[s + 1]], C_) for s in range(S_)])
     thetas = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
     jit = jitter_of(args, 0.5)
-    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, chains_per_series=C_,
-                         precision=RSV_F32_MIXED, max_steps=k, seed=3, dtau_jitter=jit)
+    level = level_of(args, True)
+    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
+    from paper_1603_08114_amd import autotune
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
+    kw = dict(chains_per_series=C_, precision=RSV_F32_MIXED, dtau_jitter=jit,
+              flags=RSV_FLAG_LEVEL_MOVE if level else 0)
+    S_t, NW_t, shape_table = autotune.best_shape(off, data["y"], data["log_rv"], h0, thetas,
+                                                 [(k, d) for d in dtau], n_sweeps=4, **kw)
+    print(f"[batched] autotuned tile shape S={S_t} NW={NW_t}: {shape_table}", file=sys.stderr,
+          flush=True)
+    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, max_steps=k, seed=3,
+                         sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
     sweep = 0
     for _ in range(10):  # 10 windows of 50 warm-up sweeps
         out = smp.sweep(sweep, 50, [(k, d) for d in dtau], update_theta=True,
@@ -295,10 +336,13 @@ def run_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32-mixed", "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": "batched RSV HMC: 512 series, T~U{500..8000}, 4 chains each, "
-                                  f"k=30, dtau jitter {jit}, FP32 leapfrog, FP64 dH/theta, "
-                                  "2000 sweeps",
+                                  f"k=30, dtau jitter {jit}, "
+                                  + ("level move, " if level else "")
+                                  + "FP32 leapfrog, FP64 dH/theta, 2000 sweeps",
                       "series": S_, "chains_per_series": C_, "k": k, "dtau_jitter": jit,
-                      "total_sites": int(Ts.sum())},
+                      "level_move": bool(level), "total_sites": int(Ts.sum()),
+                      "sites_per_lane": S_t, "waves_per_tile": NW_t},
+           "autotune_seconds_per_sweep": shape_table,
            "min_over_series": float(rate.min()), "site_updates_per_s": total_su / elapsed,
            "acceptance": float(out["accepted"].float().mean().item()),
            "dtau_range": [float(dtau.min()), float(dtau.max())]}
@@ -312,7 +356,8 @@ def run_batched(args):
         t0 = _t.perf_counter()
         for j in range(C_):
             oracle.run(data["h_true"][off[s]:off[s + 1]], data["thetas"][s], y2, r, k,
-                       float(dtau[s]), 25, seed=3, chain=s * C_ + j, jitter=jit)
+                       float(dtau[s]), 25, seed=3, chain=s * C_ + j, jitter=jit,
+                       moves=oracle.MOVE_LEVEL if level else 0)
         dt = _t.perf_counter() - t0
         res["cpu_baseline"] = {"value": T * k * 25 * C_ / dt, "unit": "site-updates/s",
                                "cores": 1, "kind": "oracle",
@@ -338,7 +383,8 @@ def run_mass(args):
     held = synth.make_batch(n_held, 1000, 16000, seed=5)
     print(f"[mass] training targets from {n_train} series", file=sys.stderr, flush=True)
     jit = jitter_of(args, 0.5)
-    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000, dtau_jitter=jit)
+    level = level_of(args, True)
+    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000, dtau_jitter=jit, level=level)
     target = -torch.log(torch.clamp(tr["var"], min=1e-12))
     net, hist, r2 = LM.train_network(train, target, tr["theta_mean"], epochs=30)
     print(f"[mass] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, R^2 {r2:.3f}", file=sys.stderr,
@@ -348,7 +394,8 @@ def run_mass(args):
     out = {}
     res_arm = {}
     for name, (prec, nt) in arms.items():
-        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25, dtau_jitter=jit)
+        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25, dtau_jitter=jit,
+                       level=level, tune_shape=True)
         res_arm[name] = r
         per = np.minimum(r["ess_h"], r["ess_theta"]) / r["elapsed"]
         out[name] = {"median_min_ess_per_s": float(np.median(per)),
@@ -356,7 +403,7 @@ def run_mass(args):
                      "median_ess_h_per_s": float(np.median(r["ess_h"] / r["elapsed"])),
                      "median_ess_theta_per_s": float(np.median(r["ess_theta"] / r["elapsed"])),
                      "seconds": r["elapsed"], "acceptance": r["acceptance"],
-                     "median_dtau": float(np.median(r["dtau"]))}
+                     "median_dtau": float(np.median(r["dtau"])), "tile_shape": r["shape"]}
         print(f"[mass] {name}: {out[name]}", file=sys.stderr, flush=True)
     # Exactness of the learned-mass FP32 h update: posterior means of h_t with
     # theta held at each series' generating value, learned FP32 vs identity FP64.
@@ -381,9 +428,10 @@ def run_mass(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed + bf16 network",
            "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
            "config": {"workload": f"learned diagonal mass: train {n_train} series, evaluate "
-                                  f"{n_held} held-out series x 4 chains, k=30, dtau jitter {jit}",
+                                  f"{n_held} held-out series x 4 chains, k=30, dtau jitter {jit}"
+                                  + (", level move" if level else ""),
                       "train_series": n_train, "held_out_series": n_held, "k": k,
-                      "dtau_jitter": jit},
+                      "dtau_jitter": jit, "level_move": bool(level)},
            "arms": out, "gain_learned_f32_vs_identity_f64": gain,
            "training": {"loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "r2": r2},
            "fixed_theta_h_means_learned_f32_vs_identity_f64": {

@@ -89,7 +89,7 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_steps) {
 
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
-           edge = 0, accept = 0, shift = 0, counters = 0, total = 0;
+           edge = 0, accept = 0, shift = 0, mass_inv = 0, mass_sqrt = 0, counters = 0, total = 0;
     int32_t max_tiles = 0;
 };
 
@@ -172,6 +172,8 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->edge = take(n_chains * kEdge * sizeof(double));
     L->accept = take(n_chains * sizeof(int32_t));
     L->shift = take(n_chains * sizeof(double));
+    L->mass_inv = take(n_data * sizeof(double));
+    L->mass_sqrt = take(n_data * sizeof(double));
     L->counters = take(kNumCounters * sizeof(uint32_t));
     L->total = off;
     L->max_tiles = static_cast<int32_t>(tiles);
@@ -202,6 +204,8 @@ struct rsv_ctx {
     double* edge = nullptr;
     int32_t* accept = nullptr;  // per chain: 1 if its current state is in h_prop
     double* shift = nullptr;    // per chain: pending level shift of the current state
+    double* mass_inv = nullptr;   // per data site 1/m_t (with a diagonal mass)
+    double* mass_sqrt = nullptr;  // per data site sqrt(m_t)
     uint32_t* counters = nullptr;
     // host mirrors of the current decomposition
     std::vector<rsv_leapfrog> lf;
@@ -311,7 +315,8 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     }
     a.y2_d = c->y2_d;
     a.lrv_d = c->pb.log_rv;
-    a.log_mass = c->log_mass;
+    a.mass_inv = c->log_mass ? c->mass_inv : nullptr;
+    a.mass_sqrt = c->log_mass ? c->mass_sqrt : nullptr;
     a.p0 = p0;
     a.seed = c->pb.seed;
     a.sweep = sweep;
@@ -470,6 +475,8 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->edge = reinterpret_cast<double*>(c->ws + L.edge);
     c->accept = reinterpret_cast<int32_t*>(c->ws + L.accept);
     c->shift = reinterpret_cast<double*>(c->ws + L.shift);
+    c->mass_inv = reinterpret_cast<double*>(c->ws + L.mass_inv);
+    c->mass_sqrt = reinterpret_cast<double*>(c->ws + L.mass_sqrt);
     c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
 
     auto bail = [&](rsv_status s) {
@@ -489,6 +496,9 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     RSV_HIP_INIT(hipMemsetAsync(c->shift, 0, c->n_chains * sizeof(double), c->stream));
     RSV_HIP_INIT(launch_prepare(c->stream, pb->y, pb->log_rv, c->n_data, c->y2_d, c->y2_f,
                                 c->lrv_f));
+    if (log_mass)
+        RSV_HIP_INIT(launch_mass_tables(c->stream, log_mass, c->n_data, c->mass_inv,
+                                        c->mass_sqrt));
     RSV_HIP_INIT(launch_validate(c->stream, pb->y, pb->log_rv, c->n_data, h, c->n_state,
                                  pb->precision, c->counters));
     std::vector<rsv_theta> th(c->n_chains);
@@ -521,7 +531,8 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
 rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
     if (!p_out) return fail(RSV_EINVAL, "p_out is NULL");
-    RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T, c->log_mass, c->pb.seed,
+    RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T,
+                           c->log_mass ? c->mass_sqrt : nullptr, c->pb.seed,
                            sweep, p_out));
     return RSV_OK;
 }

@@ -112,15 +112,8 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     }
 
     // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
-    const float* lm = MASS ? A.log_mass + cd.d_off : nullptr;
-    if constexpr (MASS) {
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
-            const double l = (t < T) ? static_cast<double>(lm[t]) : 0.0;
-            dtm[j] = static_cast<R>(dt * exp_fast(-l));
-        }
-    }
+    const double* minv = MASS ? A.mass_inv + cd.d_off : nullptr;
+    const double* msq = MASS ? A.mass_sqrt + cd.d_off : nullptr;
     if (A.p0) {
         const double* p0 = A.p0 + cd.h_off;
 #pragma unroll
@@ -136,14 +129,25 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
                       static_cast<uint64_t>(td.chain), kTagMomentum, u);
             gauss_pair(u[0], u[1], z[0], z[1]);
             gauss_pair(u[2], u[3], z[2], z[3]);
+            // the mass table is read only after this block's normals exist:
+            // loads hoisted above the generator would hold registers through it
+            if constexpr (MASS) asm volatile("" ::: "memory");
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
                 const int t = t0 + j;
                 double pm = z[q];
-                if constexpr (MASS) pm *= exp_fast(0.5 * ((t < T) ? static_cast<double>(lm[t]) : 0.0));
+                if constexpr (MASS) pm *= (t < T) ? msq[t] : 1.0;
                 p[j] = (t < T) ? static_cast<R>(pm) : R(0);
             }
+        }
+    }
+    if constexpr (MASS) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            dtm[j] = static_cast<R>(dt * ((t < T) ? minv[t] : 1.0));
         }
     }
 #pragma unroll
@@ -151,7 +155,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const int t = t0 + j;
         if (t >= td.a && t < td.b) {
             const double pj = static_cast<double>(p[j]);
-            const double im = MASS ? exp_fast(-static_cast<double>(lm[t])) : 1.0;
+            const double im = MASS ? minv[t] : 1.0;
             kin0 += 0.5 * pj * pj * im;
         }
     }
@@ -225,6 +229,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
+    // 1/m_t is read again here rather than kept live across the leapfrog loop
+    const double* minv_again = minv;
+    if constexpr (MASS) asm volatile("" : "+v"(minv_again));
     double dH = -kin0;
     double s1[5] = {0, 0, 0, 0, 0}, s0[5] = {0, 0, 0, 0, 0};
     double sy1 = 0.0, sy0 = 0.0;  // sum y^2 e^{-h} of h' and h
@@ -236,7 +243,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const double h1 = static_cast<double>(h[j]);
         const double h0 = h0d[j];
         const double pj = static_cast<double>(p[j]);
-        const double im = MASS ? exp_fast(-static_cast<double>(lm[t])) : 1.0;
+        const double im = MASS ? minv_again[t] : 1.0;
         const double rr = lrd[t];
         double d = 0.5 * pj * pj * im;
         if (RET) {
@@ -308,21 +315,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     }
 }
 
-// Occupancy hint of the trajectory kernel (waves per SIMD; 0 = compiler's
-// choice).  Set at build time.
-#ifndef RSV_TRAJ_WAVES_PER_EU
-#define RSV_TRAJ_WAVES_PER_EU 0
-#endif
-#if RSV_TRAJ_WAVES_PER_EU > 0
-#define RSV_TRAJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(RSV_TRAJ_WAVES_PER_EU)))
-#else
-#define RSV_TRAJ_OCCUPANCY
-#endif
-
 // One launch covers every tile; tiles whose chain ends inside a lane (EDGE)
 // take the variant that substitutes the end-point neighbour per site.
 template <typename R, int S, int NW, bool MASS, bool RET>
-__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) RSV_TRAJ_OCCUPANCY void k_traj(TrajArgs<R> A) {
+__device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
     static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
     static_assert(NW == 1 || NW == 2 || NW == 4 || NW == 8, "tile shapes");
     // NW = 1: four independent tiles per 256-thread block (no barriers);
@@ -339,6 +335,23 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) RSV_TRAJ_OCCUPANCY void k_
         traj_tile<R, S, NW, MASS, true, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
     else
         traj_tile<R, S, NW, MASS, false, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
+}
+
+// Identity mass.
+template <typename R, int S, int NW, bool RET>
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void k_traj(TrajArgs<R> A) {
+    traj_launch_body<R, S, NW, false, RET>(A);
+}
+
+// Diagonal mass.  Its momentum draw keeps more values live than the leapfrog
+// loop needs; for S <= 8 the register cap of four waves per SIMD moves the
+// overflow to scratch in that once-per-trajectory phase, not in the loop
+// (S = 16 needs more than the cap in the loop itself and is left uncapped).
+template <typename R, int S, int NW, bool RET>
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW)
+__attribute__((amdgpu_waves_per_eu(S <= 8 ? 4 : 1)))
+void k_traj_mass(TrajArgs<R> A) {
+    traj_launch_body<R, S, NW, true, RET>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,9 +791,23 @@ __global__ void k_clear_sel(int32_t* state_sel, double* shift, int32_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Diagonal mass tables: 1/m_t and sqrt(m_t) from the caller's ln m_t.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_mass_tables(const float* log_mass, int64_t n,
+                                                     double* inv, double* sqrt_m) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+         t += stride) {
+        const double l = static_cast<double>(log_mass[t]);
+        inv[t] = exp_fast(-l);
+        sqrt_m[t] = exp_fast(0.5 * l);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Standalone momentum refresh (same streams as the trajectory kernel).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const float* log_mass,
+__global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const double* mass_sqrt,
                                                  uint64_t seed, uint64_t sweep, double* p_out) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
@@ -794,7 +821,7 @@ __global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const 
         for (int q = 0; q < 4; ++q) {
             const int t = 4 * g + q;
             if (t >= cd.T) break;
-            const double sm = log_mass ? exp_fast(0.5 * static_cast<double>(log_mass[cd.d_off + t])) : 1.0;
+            const double sm = mass_sqrt ? mass_sqrt[cd.d_off + t] : 1.0;
             p_out[cd.h_off + t] = z[q] * sm;
         }
     }
@@ -834,10 +861,13 @@ hipError_t launch_traj_t(hipStream_t st, bool mass, bool ret, const TrajArgs<R>&
     if (a.n_list <= 0) return hipSuccess;
     constexpr int per_block = NW == 1 ? 4 : 1;
     const dim3 grid((a.n_list + per_block - 1) / per_block), block(NW == 1 ? 256 : 64 * NW);
-#define RSV_TRAJ(M, RT) hipLaunchKernelGGL((k_traj<R, S, NW, M, RT>), grid, block, 0, st, a)
-    if (ret) { if (mass) RSV_TRAJ(true, true); else RSV_TRAJ(false, true); }
-    else     { if (mass) RSV_TRAJ(true, false); else RSV_TRAJ(false, false); }
-#undef RSV_TRAJ
+    if (mass) {
+        if (ret) hipLaunchKernelGGL((k_traj_mass<R, S, NW, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_traj_mass<R, S, NW, false>), grid, block, 0, st, a);
+    } else {
+        if (ret) hipLaunchKernelGGL((k_traj<R, S, NW, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_traj<R, S, NW, false>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -1015,11 +1045,19 @@ hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
     return hipGetLastError();
 }
 
+hipError_t launch_mass_tables(hipStream_t st, const float* log_mass, int64_t n, double* inv,
+                              double* sqrt_m) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mass_tables, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, log_mass, n,
+                       inv, sqrt_m);
+    return hipGetLastError();
+}
+
 hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
-                          int32_t max_T, const float* log_mass, uint64_t seed, uint64_t sweep,
+                          int32_t max_T, const double* mass_sqrt, uint64_t seed, uint64_t sweep,
                           double* p_out) {
     const dim3 g(grid_for((max_T + 3) / 4, 256, 1024), n_chains), b(256);
-    hipLaunchKernelGGL(k_momenta, g, b, 0, st, chains, log_mass, seed, sweep, p_out);
+    hipLaunchKernelGGL(k_momenta, g, b, 0, st, chains, mass_sqrt, seed, sweep, p_out);
     return hipGetLastError();
 }
 

@@ -17,14 +17,14 @@ from collections import Counter
 from . import build as B
 
 OUT = os.path.join(B.PKG, "isa_counts.json")
-VARIANTS = {("f64", 4, 1): "IdLi4ELi1ELb0ELb1E", ("f64", 4, 2): "IdLi4ELi2ELb0ELb1E",
-            ("f64", 4, 4): "IdLi4ELi4ELb0ELb1E", ("f64", 4, 8): "IdLi4ELi8ELb0ELb1E",
-            ("f64", 8, 1): "IdLi8ELi1ELb0ELb1E", ("f64", 8, 2): "IdLi8ELi2ELb0ELb1E",
-            ("f64", 8, 4): "IdLi8ELi4ELb0ELb1E", ("f64", 8, 8): "IdLi8ELi8ELb0ELb1E",
-            ("f32", 8, 1): "IfLi8ELi1ELb0ELb1E", ("f32", 8, 2): "IfLi8ELi2ELb0ELb1E",
-            ("f32", 8, 4): "IfLi8ELi4ELb0ELb1E",
-            ("f32", 8, 8): "IfLi8ELi8ELb0ELb1E", ("f32", 16, 1): "IfLi16ELi1ELb0ELb1E",
-            ("f32", 16, 2): "IfLi16ELi2ELb0ELb1E", ("f32", 16, 4): "IfLi16ELi4ELb0ELb1E"}
+VARIANTS = {("f64", 4, 1): "IdLi4ELi1ELb1E", ("f64", 4, 2): "IdLi4ELi2ELb1E",
+            ("f64", 4, 4): "IdLi4ELi4ELb1E", ("f64", 4, 8): "IdLi4ELi8ELb1E",
+            ("f64", 8, 1): "IdLi8ELi1ELb1E", ("f64", 8, 2): "IdLi8ELi2ELb1E",
+            ("f64", 8, 4): "IdLi8ELi4ELb1E", ("f64", 8, 8): "IdLi8ELi8ELb1E",
+            ("f32", 8, 1): "IfLi8ELi1ELb1E", ("f32", 8, 2): "IfLi8ELi2ELb1E",
+            ("f32", 8, 4): "IfLi8ELi4ELb1E",
+            ("f32", 8, 8): "IfLi8ELi8ELb1E", ("f32", 16, 1): "IfLi16ELi1ELb1E",
+            ("f32", 16, 2): "IfLi16ELi2ELb1E", ("f32", 16, 4): "IfLi16ELi4ELb1E"}
 
 
 def assemble() -> str:

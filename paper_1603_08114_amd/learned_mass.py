@@ -21,8 +21,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import api, diagnostics, mass
-from ._lib import RSV_F32_MIXED, RSV_F64, THETA_KEYS
+from . import api, autotune, diagnostics, mass
+from ._lib import RSV_F32_MIXED, RSV_F64, RSV_FLAG_LEVEL_MOVE, THETA_KEYS
 
 
 def _series_view(off, C):
@@ -109,7 +109,7 @@ def chains_for(data, C):
 
 
 def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True,
-            dtau_jitter=0.0):
+            dtau_jitter=0.0, level=False, tune_shape=False):
     """One arm on one batch of series; returns measure() output plus dtau.
     update_theta=False holds every chain at its series' generating theta (an
     exactness check of the h update alone: the h-conditional mixes in a few
@@ -119,9 +119,15 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
     Ts = np.diff(off)
     h0, thetas = chains_for(data, C)
     kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed,
-              dtau_jitter=dtau_jitter)
-    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, **kw)
+              dtau_jitter=dtau_jitter, flags=RSV_FLAG_LEVEL_MOVE if level else 0)
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
+    shape = {}
+    tkw = {k_: v for k_, v in kw.items() if k_ != "max_steps"}
+    if tune_shape and net is None:
+        S_, NW_, _ = autotune.best_shape(off, data["y"], data["log_rv"], h0, thetas,
+                                         [(k, d) for d in dtau], n_sweeps=4, **tkw)
+        shape = dict(sites_per_lane=S_, waves_per_tile=NW_)
+    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, **kw, **shape)
     dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 100, S, C,
                                       update_theta=update_theta)
     log_m = None
@@ -132,20 +138,27 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
         state = smp.h.to(torch.float64).cpu().numpy()
         th_now = smp.theta.cpu().numpy()
         smp.close()
+        lm_host = log_m.cpu().numpy()
+        if tune_shape:
+            S_, NW_, _ = autotune.best_shape(off, data["y"], data["log_rv"], state, th_now,
+                                             [(k, d) for d in dtau], n_sweeps=4,
+                                             log_mass=lm_host, **tkw)
+            shape = dict(sites_per_lane=S_, waves_per_tile=NW_)
         smp = api.RSVSampler(off, data["y"], data["log_rv"], state, th_now,
-                             log_mass=log_m.cpu().numpy(), **kw)
+                             log_mass=lm_host, **kw, **shape)
     dtau, sweep, _, _ = adapt(smp, k, dtau, sweep, warm // 100, S, C, update_theta=update_theta)
     res = measure(smp, k, dtau, sweep, n, bl, off, C, update_theta=update_theta)
     res["dtau"] = dtau
     res["log_mass"] = None if log_m is None else log_m
+    res["shape"] = shape
     smp.close()
     return res
 
 
-def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0, dtau_jitter=0.0):
+def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0, dtau_jitter=0.0, level=False):
     """Pooled per-site posterior mean and variance from identity FP64 chains."""
     res = run_arm(data, C, k, RSV_F64, None, seed=seed, warm=warm, n=n, bl=40,
-                  dtau_jitter=dtau_jitter)
+                  dtau_jitter=dtau_jitter, level=level)
     return res
 
 
