@@ -575,6 +575,13 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         return st != RSV_OK ? st : settle(c);
     }
     const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
+    const bool acc = trace && (trace->h_batch_sum || trace->h_sq_sum);
+    // batch-sum row of the state after sweep i of this call
+    auto batch_row = [&](int32_t i) -> double* {
+        return trace->h_batch_sum
+                   ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
+                   : nullptr;
+    };
     for (int32_t i = 0; i < n_sweeps; ++i) {
         const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;
         double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
@@ -586,14 +593,10 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
                             update_theta ? 1 : 0, tt, ht, nullptr);
         if (st != RSV_OK) return st;
-        if (trace && (trace->h_batch_sum || trace->h_sq_sum)) {
-            double* bs = trace->h_batch_sum
-                             ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
-                             : nullptr;
-            RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
-                                      c->h_prop, level_moves(c) ? c->shift : nullptr, bs,
-                                      trace->h_sq_sum, c->pb.precision));
-        }
+        if (acc)
+            RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept,
+                                      c->h, c->h_prop, level_moves(c) ? c->shift : nullptr,
+                                      batch_row(i), trace->h_sq_sum, c->pb.precision));
     }
     return settle(c);
 }

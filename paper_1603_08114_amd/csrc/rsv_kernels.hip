@@ -416,6 +416,20 @@ constexpr int kAcceptBlock = kThetaBlocks;
 constexpr int kMoveBlock = kThetaBlocks + 1;            // block 0 of the move stream
 constexpr int kMoveGammaBlock = kMoveBlock + 1;         // its Gamma attempts
 constexpr int kDrawBlocks = kMoveGammaBlock + kGammaTries;
+// Gamma attempts evaluated in parallel; the rest only when all of these are
+// rejected (Marsaglia-Tsang accepts > 99% of attempts for shapes >= 1.5).
+#ifndef RSV_GAMMA_PARALLEL
+#define RSV_GAMMA_PARALLEL 4
+#endif
+constexpr int kGammaParallel = RSV_GAMMA_PARALLEL;
+
+__device__ inline bool gamma_block(int b) {
+    return (b >= kGammaEtaBlock && b < kThetaBlocks) || b >= kMoveGammaBlock;
+}
+__device__ inline int gamma_index(int b) {  // attempt number within its Gamma draw
+    if (b >= kMoveGammaBlock) return b - kMoveGammaBlock;
+    return b < kGammaUBlock ? b - kGammaEtaBlock : b - kGammaUBlock;
+}
 
 struct ThetaDraws {
     double z_mu, z_phi, u_phi, z_xi, log_u_accept, z_c, u_c;
@@ -589,7 +603,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         for (int b = tid; b < kDrawBlocks; b += NT) {
             const bool need = b < kThetaBlocks ? need_theta
                                                : (b == kAcceptBlock ? need_accept : need_move);
-            if (need)
+            if (need && !(gamma_block(b) && gamma_index(b) >= kGammaParallel))
                 theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
                                  A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
         }
@@ -623,6 +637,25 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         tot[q] = r.s + r.c;
     }
 
+    // a Gamma draw whose parallel attempts were all rejected continues serially
+    // up to its first accepted attempt, so the first accepted attempt is the
+    // same one a fully parallel evaluation would find
+    {
+        const double n = static_cast<double>(cd.T);
+        const int firsts[3] = {kGammaEtaBlock, kGammaUBlock, kMoveGammaBlock};
+        const bool needed[3] = {A.do_theta != 0, A.do_theta != 0,
+                                A.do_theta && A.level_move != 0};
+        for (int gi = 0; gi < 3; ++gi) {
+            if (!needed[gi]) continue;
+            bool found = false;
+            for (int i = 0; i < kGammaParallel; ++i) found = found || draws.g_ok[firsts[gi] + i];
+            for (int i = kGammaParallel; i < kGammaTries && !found; ++i) {
+                theta_draw_block(firsts[gi] + i, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+                found = draws.g_ok[firsts[gi] + i];
+            }
+        }
+    }
     const rsv_theta th = A.theta[c];
     bool use_prop = false;
     if (A.do_metropolis) {
@@ -721,7 +754,7 @@ __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
                 if (ht) ht[t] = v;
                 const double vd = static_cast<double>(v);
                 if (bs) bs[t] += vd;
-                if (sq) sq[t] += vd * vd;
+                if (sq) sq[t] = __builtin_fma(vd, vd, sq[t]);
             }
             __syncthreads();
         }
@@ -761,7 +794,7 @@ __global__ __launch_bounds__(256) void k_accumulate(const ChainDesc* chains,
         const int64_t i = cd.h_off + t;
         const double v = static_cast<double>(state_at(src, t, sft));
         if (batch_sum) batch_sum[i] += v;
-        if (sq_sum) sq_sum[i] += v * v;
+        if (sq_sum) sq_sum[i] = __builtin_fma(v, v, sq_sum[i]);
     }
 }
 
