@@ -408,7 +408,7 @@ def run_mass(args):
     # Exactness of the learned-mass FP32 h update: posterior means of h_t with
     # theta held at each series' generating value, learned FP32 vs identity FP64.
     # (With theta updated, h_t means inherit theta's slow mixing and short-batch
-    # standard errors are too small to judge them.)
+    # standard errors are too small to compare them.)
     fixed = {}
     for name, (prec, nt, sd) in {"identity_f64": (RSV_F64, None, 6),
                                  "learned_f32": (RSV_F32_MIXED, net, 7)}.items():

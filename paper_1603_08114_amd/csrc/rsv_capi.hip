@@ -324,13 +324,18 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.chain_edge = c->edge;
     a.jitter = c->pb.dtau_jitter;
     a.shift = level_moves(c) ? c->shift : nullptr;
+    a.acc_sum = nullptr;
+    a.acc_sq = nullptr;
     a.terms = c->pb.terms;
     return a;
 }
 
 template <typename R>
-rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0) {
+rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, double* acc_sum,
+                           double* acc_sq) {
     TrajArgs<R> a = traj_args<R>(c, sweep, p0);
+    a.acc_sum = acc_sum;
+    a.acc_sq = acc_sq;
     const bool mass = c->log_mass != nullptr;
     const bool timed = c->ev_used < c->ev_start.size();
     if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
@@ -366,11 +371,15 @@ FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do
     return f;
 }
 
+// acc_sum / acc_sq (or nullptr): accumulators that receive the state this
+// trajectory starts from, i.e. the result of the previous sweep.
 rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
                           double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
-                          void* h_trace, double* stats_out) {
-    const rsv_status st = c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0)
-                                                     : launch_traj_all<float>(c, sweep, p0);
+                          void* h_trace, double* stats_out, double* acc_sum = nullptr,
+                          double* acc_sq = nullptr) {
+    const rsv_status st =
+        c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0, acc_sum, acc_sq)
+                                   : launch_traj_all<float>(c, sweep, p0, acc_sum, acc_sq);
     if (st != RSV_OK) return st;
     FinalizeArgs f = finalize_args(c, sweep, 1, do_theta);
     f.log_u = log_u;
@@ -590,14 +599,17 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         void* ht = (trace && trace->h)
                        ? static_cast<char*>(trace->h) + static_cast<size_t>(i) * c->n_state * elem
                        : nullptr;
+        // the trajectory of sweep i accumulates the state after sweep i - 1
+        double* acc_sum = (acc && i > 0) ? batch_row(i - 1) : nullptr;
+        double* acc_sq = (acc && i > 0) ? trace->h_sq_sum : nullptr;
         st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
-                            update_theta ? 1 : 0, tt, ht, nullptr);
+                            update_theta ? 1 : 0, tt, ht, nullptr, acc_sum, acc_sq);
         if (st != RSV_OK) return st;
-        if (acc)
-            RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept,
-                                      c->h, c->h_prop, level_moves(c) ? c->shift : nullptr,
-                                      batch_row(i), trace->h_sq_sum, c->pb.precision));
     }
+    if (acc && n_sweeps > 0)  // the state after the last sweep
+        RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
+                                  c->h_prop, level_moves(c) ? c->shift : nullptr,
+                                  batch_row(n_sweeps - 1), trace->h_sq_sum, c->pb.precision));
     return settle(c);
 }
 

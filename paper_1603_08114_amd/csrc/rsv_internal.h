@@ -72,6 +72,8 @@ struct TrajArgs {
     double jitter;              // step-size jitter j (0: fixed dtau)
     const double* shift;        // per chain: pending level shift of the current
                                 // state (value = stored + shift), or nullptr
+    double* acc_sum;            // per state entry: add the state the trajectory
+    double* acc_sq;             // starts from, and its square (or nullptr)
     int32_t terms;
 };
 

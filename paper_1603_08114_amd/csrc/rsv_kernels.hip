@@ -110,6 +110,21 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         dc[j] = static_cast<R>(-dt * (c_base - rr * inv_su));
         ds[j] = RET ? static_cast<R>(0.5 * dt * yy) : R(0);
     }
+    // batch-means accumulators of the starting state (the previous sweep's
+    // result) on the exact sites: the read-modify-writes overlap with the
+    // momentum draw instead of costing a separate pass over the state
+    if (A.acc_sum || A.acc_sq) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            if (t >= td.a && t < td.b) {
+                const double v = static_cast<double>(h[j]);
+                const int64_t i = cd.h_off + t;
+                if (A.acc_sum) A.acc_sum[i] += v;
+                if (A.acc_sq) A.acc_sq[i] = __builtin_fma(v, v, A.acc_sq[i]);
+            }
+        }
+    }
 
     // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
     const double* minv = MASS ? A.mass_inv + cd.d_off : nullptr;
