@@ -302,7 +302,10 @@ def _compare_runs(gpu_acc, gpu_dh, gpu_theta, ref, seed, chain, first):
             print(f"near-tie at sweep {first + i}: dH={ref['dH'][i]!r} log u={lu!r}")
             return i  # chains legitimately diverge from here
         assert bool(gpu_acc[i]) == bool(ref["accepted"][i]), (chain, i)
-        assert abs(gpu_dh[i] - ref["dH"][i]) <= 1e-9 * max(1.0, abs(ref["dH"][i]))
+        if np.isfinite(ref["dH"][i]):
+            assert abs(gpu_dh[i] - ref["dH"][i]) <= 1e-9 * max(1.0, abs(ref["dH"][i]))
+        else:  # a diverged trajectory: both sides non-finite, both reject
+            assert not np.isfinite(gpu_dh[i]) and not gpu_acc[i]
         np.testing.assert_allclose(gpu_theta[i], ref["theta_trace"][i], rtol=1e-10, atol=1e-13)
     return n
 
@@ -469,3 +472,35 @@ def test_tile_shapes_give_the_same_trajectory():
         outs.append(smp.h.cpu().numpy())
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("S,NW,k,dt", [(4, 1, 123, 0.004), (8, 1, 251, 0.002), (8, 4, 1, 0.3),
+                                       (4, 4, 2, 0.2)])
+def test_extreme_step_counts(S, NW, k, dt):
+    """The largest k a tile shape accepts (halo = all but 8 sites of the tile)
+    and single/double steps, over ragged chains spanning several tiles."""
+    Ts, C = [1000, 300, 3], 2
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW)
+    dh, acc = smp.trajectory(9, (k, dt))
+    h_gpu, dh, acc = smp.h.cpu().numpy(), dh.cpu().numpy(), acc.cpu().numpy()
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        ref = oracle.trajectory(h0[sl], ys[s] ** 2, rs[s], th[c], k, dt, seed=smp.pb.seed,
+                                sweep=9, chain=c)
+        assert abs(dh[c] - ref["dH"]) <= 1e-9 * max(1.0, abs(ref["dH"]))
+        if abs(ref["dH"] + oracle.log_u(smp.pb.seed, 9, c)) > NEAR_TIE:
+            assert bool(acc[c]) == ref["accepted"]
+            assert rel_inf(h_gpu[sl], ref["h"]) <= 1e-12
+
+
+def test_many_minimum_length_chains():
+    """4096 chains of T = 3 (one partial lane each), several sweeps with theta."""
+    Ts, C, k, dt, n = [3] * 1024, 4, 10, 0.1, 12
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k)
+    out = smp.sweep(0, n, (k, dt), update_theta=True)
+    acc = out["accepted"].cpu().numpy()
+    dh = out["delta_h"].cpu().numpy()
+    tht = out["theta"].cpu().numpy()
+    for c in (0, 1, 2047, 4095):
+        s, sl = chain_slices(offsets, C)[c]
+        ref = oracle.run(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, seed=smp.pb.seed, chain=c)
+        _compare_runs(acc[:, c], dh[:, c], tht[:, c], ref, smp.pb.seed, c, 0)
