@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--dtau", type=float, default=0.0, help="0 = tune to ~80%% acceptance")
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--sites-per-lane", type=int, default=8)
-    ap.add_argument("--waves-per-tile", type=int, default=4)
+    ap.add_argument("--sites-per-lane", type=int, default=0,
+                    help="tile shape: sites per lane (0 = the library default: 4 for f64, 8 for f32)")
+    ap.add_argument("--waves-per-tile", type=int, default=0, help="0 = the library default (4)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--level-move", type=int, default=-1, choices=[-1, 0, 1],
                     help="level move of (h, mu, xi) before each theta update; -1 = the "
@@ -451,7 +452,7 @@ def run_precision(args):
     import torch
     import synth
     from paper_1603_08114_amd import api, diagnostics
-    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64, RSV_FLAG_LEVEL_MOVE
     T, k = args.T, args.k
     n = max(args.steps, 50)
     theta = dict(synth.THETA_STAR)
@@ -488,7 +489,8 @@ def run_precision(args):
         for prec, sd in ((RSV_F32_MIXED, 1), (RSV_F64, 2)):
             smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k,
                                  seed=args.seed + sd + (10 if upd else 0), precision=prec,
-                                 dtau_jitter=jitter_of(args, 0.5))
+                                 dtau_jitter=jitter_of(args, 0.5),
+                                 flags=RSV_FLAG_LEVEL_MOVE if level_of(args, True) else 0)
             smp.sweep(0, 200, lf, update_theta=upd, record=())
             o = smp.sweep(200, n_chain, lf, update_theta=upd, record=("theta",), batch_len=bl)
             bm = o["h_batch_sum"] / bl
@@ -562,7 +564,8 @@ def main():
     smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
                          precision=prec, sites_per_lane=args.sites_per_lane,
                          waves_per_tile=args.waves_per_tile, dtau_jitter=jit)
-    S, NW = args.sites_per_lane, args.waves_per_tile
+    S = args.sites_per_lane or (4 if args.precision == "f64" else 8)
+    NW = args.waves_per_tile or 4
     print(f"[bench] T={T} k={k} precision={args.precision} S={S} NW={NW}", file=sys.stderr,
           flush=True)
 

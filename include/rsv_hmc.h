@@ -110,8 +110,9 @@ typedef struct {
     int32_t terms;              /* RSV_TERM_* bit set, at least one bit        */
     int32_t max_steps;          /* largest k any later call will use (>= 1)    */
     int32_t sites_per_lane;     /* tile shape of the trajectory kernel: sites
-                                   held by each lane (0 = library default;
-                                   RSV_F64: 4 or 8, RSV_F32_MIXED: 8 or 16)    */
+                                   held by each lane (0 = library default: 4
+                                   for RSV_F64, 8 for RSV_F32_MIXED; compiled:
+                                   RSV_F64 4 or 8, RSV_F32_MIXED 8 or 16)       */
     int32_t waves_per_tile;     /* wavefronts per tile (0 = default 4; compiled
                                    (S, NW): F64 S in {4, 8} x NW in {1, 2, 4,
                                    8}; F32 S = 8 x NW in {1, 2, 4, 8} and

@@ -69,9 +69,21 @@ struct TileShared {
     double up1[NW], up0[NW];
 };
 
-template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET>
+// FP64 tiles keep the starting h, y^2 and ln RV of their sites in LDS for
+// the dH pass after the leapfrog loop (laid out [quantity][site j][lane],
+// each lane reading back only what it wrote), so that pass does not re-read
+// them from memory: the tiles in flight on one XCD hold more than its L2.
+// Enabled while a block's copy fits 48 KB (S * NW * tiles per block <= 32).
+template <typename R, int S, int NW, int TPB>
+struct Stage {
+    static constexpr bool on = sizeof(R) == sizeof(double) && S * NW * TPB <= 32;
+    static constexpr int n = on ? 3 * S * 64 * NW : 1;
+};
+
+template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET, bool STAGE>
 __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW>& sh,
-                                          const int tile_id, const int wv, const int lane) {
+                                          const int tile_id, const int wv, const int lane,
+                                          double* stage) {
     const TileDesc td = A.tiles[tile_id];
     const ChainDesc cd = A.chains[td.chain];
     const rsv_theta th = A.theta[td.chain];
@@ -109,6 +121,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const double rr = live ? static_cast<double>(lr[t]) : 0.0;
         dc[j] = static_cast<R>(-dt * (c_base - rr * inv_su));
         ds[j] = RET ? static_cast<R>(0.5 * dt * yy) : R(0);
+        if constexpr (STAGE) {
+            constexpr int NT = 64 * NW;
+            const int g = wv * kWave + lane;
+            stage[(0 * S + j) * NT + g] = static_cast<double>(h[j]);
+            stage[(1 * S + j) * NT + g] = yy;
+            stage[(2 * S + j) * NT + g] = rr;
+        }
     }
     // batch-means accumulators of the starting state (the previous sweep's
     // result) on the exact sites: the read-modify-writes overlap with the
@@ -224,11 +243,16 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     //      sufficient statistics of the proposal and of the current state ----
     const double* y2d = A.y2_d + cd.d_off;
     const double* lrd = A.lrv_d + cd.d_off;
+    constexpr int NTS = 64 * NW;
+    const int gl = wv * kWave + lane;
     double h0d[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
-        h0d[j] = (t < T) ? static_cast<double>(state_at(hc, t, shift)) : 0.0;
+        if constexpr (STAGE)
+            h0d[j] = stage[(0 * S + j) * NTS + gl];  // 0 beyond T, as below
+        else
+            h0d[j] = (t < T) ? static_cast<double>(state_at(hc, t, shift)) : 0.0;
     }
     double h1_up = static_cast<double>(from_upper(h[0]));
     double h0_up = from_upper(h0d[0]);
@@ -259,10 +283,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const double h0 = h0d[j];
         const double pj = static_cast<double>(p[j]);
         const double im = MASS ? minv_again[t] : 1.0;
-        const double rr = lrd[t];
+        const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
         double d = 0.5 * pj * pj * im;
         if (RET) {
-            const double ye0 = y2d[t] * exp_fast(-h0);
+            const double ye0 = (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) * exp_fast(-h0);
             const double x10 = exp_fast(h0 - h1);  // e^{-h1} / e^{-h0}
             d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
             sy1 += ye0 * x10;
@@ -340,16 +364,21 @@ __device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
     // NW > 1: one tile per block of NW wavefronts, so a barrier never spans
     // tiles of chains with different k.
     constexpr int kTilesPerBlock = NW == 1 ? 4 : 1;
+    using St = Stage<R, S, NW, kTilesPerBlock>;
     __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
+    __shared__ double stage_all[kTilesPerBlock][St::n];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv_blk = threadIdx.x / kWave;
     const int w = blockIdx.x * kTilesPerBlock + wv_blk / NW;
     if (w >= A.n_list) return;  // uniform over the tile's wavefronts
     const int tile_id = A.tile_first + w;
+    double* stage = stage_all[wv_blk / NW];
     if (A.tiles[tile_id].edge)
-        traj_tile<R, S, NW, MASS, true, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
+        traj_tile<R, S, NW, MASS, true, RET, St::on>(A, sh_all[wv_blk / NW], tile_id,
+                                                     wv_blk % NW, lane, stage);
     else
-        traj_tile<R, S, NW, MASS, false, RET>(A, sh_all[wv_blk / NW], tile_id, wv_blk % NW, lane);
+        traj_tile<R, S, NW, MASS, false, RET, St::on>(A, sh_all[wv_blk / NW], tile_id,
+                                                      wv_blk % NW, lane, stage);
 }
 
 // Identity mass.
@@ -729,7 +758,9 @@ __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
 // ---------------------------------------------------------------------------
 template <typename R, int S, bool MASS, bool RET>
 __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
+    using St = Stage<R, S, 4, 1>;
     __shared__ TileShared<R, 4> sh;
+    __shared__ double stage[St::n];
     __shared__ Comp part[4][kNQ];
     __shared__ ThetaDraws draws;
     const int c = blockIdx.x;
@@ -743,9 +774,9 @@ __global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
         TrajArgs<R> A = RA.traj;
         A.sweep = RA.first_sweep + static_cast<uint64_t>(i);
         if (edge)
-            traj_tile<R, S, 4, MASS, true, RET>(A, sh, tile_id, wv, lane);
+            traj_tile<R, S, 4, MASS, true, RET, St::on>(A, sh, tile_id, wv, lane, stage);
         else
-            traj_tile<R, S, 4, MASS, false, RET>(A, sh, tile_id, wv, lane);
+            traj_tile<R, S, 4, MASS, false, RET, St::on>(A, sh, tile_id, wv, lane, stage);
         __syncthreads();
         FinalizeArgs F = RA.fin;
         F.sweep = A.sweep;
@@ -929,9 +960,10 @@ bool traj_shape_available(int precision, int S, int NW) {
     return (S == 8 && nw) || (S == 16 && (NW == 1 || NW == 2 || NW == 4));
 }
 void traj_default_shape(int precision, int* S, int* NW) {
-    *S = 8;
+    // fastest measured on a long series: FP64 (4, 4) (fewer registers, five
+    // waves per SIMD), FP32 (8, 4)
+    *S = precision == RSV_F64 ? 4 : 8;
     *NW = 4;
-    (void)precision;
 }
 
 hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,

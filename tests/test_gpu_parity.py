@@ -401,9 +401,13 @@ def test_poisoned_state_reported_by_check():
     assert st == -5
 
 
-def test_batch_mean_accumulators_match_recorded_trace():
+@pytest.mark.parametrize("Ts,flags", [([700, 1500], 0), ([700, 1000], 0), ([700, 1000], 1)])
+def test_batch_mean_accumulators_match_recorded_trace(Ts, flags):
+    """Per-kernel sweeps (the next trajectory accumulates the previous state,
+    the last state by a separate pass) and resident sweeps (all chains fit
+    one tile; flags 0) against the recorded trace."""
     k, dt, n, bl = 20, 0.05, 30, 7
-    smp, offsets, ys, rs, h0, th = sampler([700, 1500], 2, k=k)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, 2, k=k, flags=flags)
     out = smp.sweep(0, n, (k, dt), update_theta=True, record=(), record_h=True, batch_len=bl)
     h = out["h"].cpu().numpy()
     bs = out["h_batch_sum"].cpu().numpy()
@@ -434,7 +438,8 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter, flags):
     for path in (0, RSV_FLAG_NO_RESIDENT):
         smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                              chains_per_series=C, precision=precision, max_steps=k, seed=4,
-                             flags=flags | path, dtau_jitter=dtau_jitter)
+                             flags=flags | path, dtau_jitter=dtau_jitter, sites_per_lane=8,
+                             waves_per_tile=4)
         o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True, batch_len=7)
         o["state"] = smp.h.clone()
         o["theta_final"] = smp.theta.clone()
