@@ -79,10 +79,6 @@ __device__ __forceinline__ double exp_force(double x) {
     return __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
 }
 
-// e^x - 1 with an absolute (not relative) error of a few ulp of max(1, e^x):
-// enough wherever the result is multiplied into a sum of O(1) terms.
-__device__ __forceinline__ double expm1_abs(double x) { return exp_fast(x) - 1.0; }
-
 // ln u for u in (0, 1]: u = 2^e m with m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716, by its Taylor
 // series through s^19 (truncation < 3e-17 relative).

@@ -462,6 +462,8 @@ constexpr int kMoveGammaBlock = kMoveBlock + 1;         // its Gamma attempts
 constexpr int kDrawBlocks = kMoveGammaBlock + kGammaTries;
 // Gamma attempts evaluated in parallel; the rest only when all of these are
 // rejected (Marsaglia-Tsang accepts > 99% of attempts for shapes >= 1.5).
+// (A build-time knob: the draws do not depend on it, only how many attempts
+// are evaluated before the serial continuation.)
 #ifndef RSV_GAMMA_PARALLEL
 #define RSV_GAMMA_PARALLEL 4
 #endif
