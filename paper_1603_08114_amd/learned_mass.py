@@ -22,7 +22,7 @@ import numpy as np
 import torch
 
 from . import api, autotune, diagnostics, mass
-from ._lib import RSV_F32_MIXED, RSV_F64, RSV_FLAG_LEVEL_MOVE, THETA_KEYS
+from ._lib import RSV_F64, RSV_FLAG_LEVEL_MOVE
 
 
 def _series_view(off, C):

@@ -102,3 +102,16 @@ def test_null_context_is_a_state_error():
     assert lib.rsv_hmc_trajectory(None, 0, lf, None, None, None, None) == _lib.RSV_ESTATE
     assert lib.rsv_theta_update(None, 0, None) == _lib.RSV_ESTATE
     assert lib.rsv_hmc_sweep(None, 0, 1, lf, 1, None) == _lib.RSV_ESTATE
+
+
+def test_autotune_cache_key_buckets():
+    """Host logic of the tile-shape autotuner: problems in one (precision, k,
+    T bucket, chain-count bucket) share a cache entry."""
+    from paper_1603_08114_amd import autotune
+    a = autotune.cache_key(0, 30, [0, 700, 1500], 4)
+    b = autotune.cache_key(0, 30, [0, 1024, 2000], 4)
+    assert a == b == "p0|k30|T1024|c8"
+    assert autotune.cache_key(0, 30, [0, 2049], 4) == "p0|k30|T4096|c4"
+    assert autotune.cache_key(1, 30, [0, 700, 1500], 4) != a
+    assert autotune.cache_key(0, 20, [0, 700, 1500], 4) != a
+    assert {S for S, _ in autotune.SHAPES[_lib.RSV_F64]} == {4, 8}

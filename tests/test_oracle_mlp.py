@@ -5,7 +5,6 @@ finite differences of the FP64 (unrounded) loss; Adam against torch.optim.Adam;
 GELU against its definition; feature windows against direct indexing.
 """
 import numpy as np
-import pytest
 import torch
 
 from oracle import mlp_oracle as M
