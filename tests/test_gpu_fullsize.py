@@ -1,13 +1,14 @@
 """Parity at the full sizes and launch configurations the benchmark times.
 
-* Single series T = 2^22, k = 50, FP64, tile (8, 4), the tuned step size: one
+* Single series T = 2^22, k = 50, FP64, tiles (4, 4) (the default) and (8, 4),
+  the tuned step size: one
   trajectory on the library's own random streams against the oracle's run of
   the whole series (h' at every site rel <= 1e-12, dH abs <= 1e-9 relative to
   max(1, |dH|), the accept decision, then the theta update from the
   GPU-reduced statistics).
 * The same series in FP32-mixed on injected momenta: the FP32 error bounds.
 * The batched layout (512 series x 4 chains, T ~ U{500..8000}, k = 30, FP32,
-  tile (8, 2)) and the held-out layout of the mass workload (1024 series x 4
+  tiles (8, 1) and (8, 2), the shapes the autotuner picks there) and the held-out layout of the mass workload (1024 series x 4
   chains, T ~ U{1000..16000}, FP64, diagonal mass, tile (4, 4)): sampled
   chains (shortest, median, longest, plus a few seeded ones) against the
   oracle run on that chain alone.
@@ -34,10 +35,11 @@ def long_series():
     return th, y, r, h
 
 
-def test_long_series_fp64_trajectory_and_theta(long_series):
+@pytest.mark.parametrize("S,NW", [(4, 4), (8, 4)])
+def test_long_series_fp64_trajectory_and_theta(long_series, S, NW):
     th, y, r, h = long_series
     smp = api.RSVSampler([0, T_LONG], y, r, h, th, max_steps=K_LONG, seed=2,
-                         sites_per_lane=8, waves_per_tile=4)
+                         sites_per_lane=S, waves_per_tile=NW)
     dh, acc = smp.trajectory(7, (K_LONG, DT_LONG))
     h_gpu = smp.h.cpu().numpy()
     ref = oracle.trajectory(h, y * y, r, th, K_LONG, DT_LONG, seed=2, sweep=7, chain=0)
@@ -82,7 +84,8 @@ def _sampled(Ts, extra, seed):
     return sorted(picks)
 
 
-def test_batched_layout_fp32_sampled_chains():
+@pytest.mark.parametrize("NW", [1, 2])
+def test_batched_layout_fp32_sampled_chains(NW):
     S_, C, k, dt = 512, 4, 30, 0.03
     data = synth.make_batch(S_, 500, 8000, seed=3)
     off = data["offsets"]
@@ -91,7 +94,7 @@ def test_batched_layout_fp32_sampled_chains():
     ths = [data["thetas"][s] for s in range(S_) for _ in range(C)]
     smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, ths, chains_per_series=C,
                          precision=RSV_F32_MIXED, max_steps=k, seed=3, sites_per_lane=8,
-                         waves_per_tile=2)
+                         waves_per_tile=NW)
     p0 = smp.momenta(11).cpu().numpy()
     dh, acc = smp.trajectory(11, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -1e9))
     h32 = smp.h.cpu().numpy().astype(np.float64)
