@@ -152,7 +152,10 @@ typedef struct {
 typedef struct rsv_ctx rsv_ctx;
 
 /* Bytes of device workspace rsv_hmc_init needs for this problem (0 if the
- * problem is invalid; see rsv_last_error). */
+ * problem is invalid; see rsv_last_error): the proposal state buffer, y^2
+ * (and FP32 copies on the mixed path), the tile descriptors and per-tile
+ * partials, per-chain selectors and level shifts, and 16 bytes per data site
+ * for the diagonal-mass tables (reserved whether or not a mass is given). */
 size_t rsv_hmc_workspace_bytes(const rsv_problem *pb);
 
 /* Number of state entries, C * offsets[S] (0 if invalid). */
@@ -165,7 +168,8 @@ int64_t rsv_hmc_state_size(const rsv_problem *pb);
  *   theta    device, S*C rsv_theta, initial values; updated in place.
  *   log_mass device, offsets[S] floats: log of the diagonal mass m_t of each
  *            series-site (shared by the chains of a series), or NULL for
- *            m = 1 (the paper's kinetic term 1/2 sum p^2).
+ *            m = 1 (the paper's kinetic term 1/2 sum p^2).  Read once here:
+ *            1/m_t and sqrt(m_t) are kept in the workspace.
  *   workspace, ws_bytes  device scratch of at least rsv_hmc_workspace_bytes.
  *   hip_stream  hipStream_t to enqueue on (NULL = the null stream).
  * Validates the problem on the host and the data, h and theta on the device
