@@ -142,7 +142,11 @@ typedef struct {
                             state precision (FP64 or FP32)                      */
     /* Moment accumulators for runs too long to store (batch means): after
      * sweep i of the call, h is added to h_batch_sum[(i / batch_len) * n_state
-     * + site] and h^2 to h_sq_sum[site] (FP64; the caller zeroes them). */
+     * + site] and h^2 to h_sq_sum[site] (FP64; the caller zeroes them).  When
+     * the sweeps run one launch per kernel (not every chain fits one tile, or
+     * RSV_FLAG_NO_RESIDENT) the states of a batch are summed in FP32 and the
+     * batch total is added to these arrays (relative error ~ batch_len *
+     * 6e-8); resident sweeps add every state in FP64. */
     double *h_batch_sum; /* device, ceil(n_sweeps / batch_len) * n_state, or NULL */
     double *h_sq_sum;    /* device, n_state, or NULL                            */
     int32_t batch_len;   /* sweeps per batch (>= 1 when h_batch_sum is set)    */

@@ -89,7 +89,8 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_steps) {
 
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
-           edge = 0, accept = 0, shift = 0, mass_inv = 0, mass_sqrt = 0, counters = 0, total = 0;
+           edge = 0, accept = 0, shift = 0, mass_inv = 0, mass_sqrt = 0, acc = 0, counters = 0,
+           total = 0;
     int32_t max_tiles = 0;
 };
 
@@ -174,6 +175,7 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->shift = take(n_chains * sizeof(double));
     L->mass_inv = take(n_data * sizeof(double));
     L->mass_sqrt = take(n_data * sizeof(double));
+    L->acc = take(2 * n_state * sizeof(float));
     L->counters = take(kNumCounters * sizeof(uint32_t));
     L->total = off;
     L->max_tiles = static_cast<int32_t>(tiles);
@@ -206,6 +208,7 @@ struct rsv_ctx {
     double* shift = nullptr;    // per chain: pending level shift of the current state
     double* mass_inv = nullptr;   // per data site 1/m_t (with a diagonal mass)
     double* mass_sqrt = nullptr;  // per data site sqrt(m_t)
+    float* acc_f = nullptr;       // per state entry: FP32 batch sum, then batch sum of squares
     uint32_t* counters = nullptr;
     // host mirrors of the current decomposition
     std::vector<rsv_leapfrog> lf;
@@ -331,8 +334,8 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
 }
 
 template <typename R>
-rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, double* acc_sum,
-                           double* acc_sq) {
+rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, float* acc_sum,
+                           float* acc_sq) {
     TrajArgs<R> a = traj_args<R>(c, sweep, p0);
     a.acc_sum = acc_sum;
     a.acc_sq = acc_sq;
@@ -375,8 +378,8 @@ FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do
 // trajectory starts from, i.e. the result of the previous sweep.
 rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
                           double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
-                          void* h_trace, double* stats_out, double* acc_sum = nullptr,
-                          double* acc_sq = nullptr) {
+                          void* h_trace, double* stats_out, float* acc_sum = nullptr,
+                          float* acc_sq = nullptr) {
     const rsv_status st =
         c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0, acc_sum, acc_sq)
                                    : launch_traj_all<float>(c, sweep, p0, acc_sum, acc_sq);
@@ -486,6 +489,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->shift = reinterpret_cast<double*>(c->ws + L.shift);
     c->mass_inv = reinterpret_cast<double*>(c->ws + L.mass_inv);
     c->mass_sqrt = reinterpret_cast<double*>(c->ws + L.mass_sqrt);
+    c->acc_f = reinterpret_cast<float*>(c->ws + L.acc);
     c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
 
     auto bail = [&](rsv_status s) {
@@ -585,12 +589,25 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
     }
     const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
     const bool acc = trace && (trace->h_batch_sum || trace->h_sq_sum);
-    // batch-sum row of the state after sweep i of this call
-    auto batch_row = [&](int32_t i) -> double* {
+    // The states of one batch are summed in FP32 buffers of the workspace
+    // (half the read-modify-write traffic of FP64 sums, which at tens of
+    // millions of states costs more than the trajectory) and added to the
+    // caller's FP64 arrays at the end of each batch.
+    float* acc_sum_f = c->acc_f;
+    float* acc_sq_f = c->acc_f + c->n_state;
+    // without batch sums, the squares are flushed every 64 sweeps
+    const int32_t bl = (trace && trace->h_batch_sum) ? trace->batch_len : 64;
+    auto batch_row = [&](int32_t i) -> double* {  // batch-sum row of the state after sweep i
         return trace->h_batch_sum
                    ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
                    : nullptr;
     };
+    auto flush = [&](int32_t i) -> hipError_t {  // end of the batch holding sweep i
+        return launch_flush(c->stream, c->n_state, acc_sum_f, acc_sq_f, batch_row(i),
+                            trace->h_sq_sum);
+    };
+    if (acc && n_sweeps > 0)  // zero the FP32 buffers
+        RSV_HIP(launch_flush(c->stream, c->n_state, acc_sum_f, acc_sq_f, nullptr, nullptr));
     for (int32_t i = 0; i < n_sweeps; ++i) {
         const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;
         double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
@@ -600,16 +617,19 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
                        ? static_cast<char*>(trace->h) + static_cast<size_t>(i) * c->n_state * elem
                        : nullptr;
         // the trajectory of sweep i accumulates the state after sweep i - 1
-        double* acc_sum = (acc && i > 0) ? batch_row(i - 1) : nullptr;
-        double* acc_sq = (acc && i > 0) ? trace->h_sq_sum : nullptr;
+        const bool add = acc && i > 0;
         st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
-                            update_theta ? 1 : 0, tt, ht, nullptr, acc_sum, acc_sq);
+                            update_theta ? 1 : 0, tt, ht, nullptr, add ? acc_sum_f : nullptr,
+                            add ? acc_sq_f : nullptr);
         if (st != RSV_OK) return st;
+        if (add && (i - 1) % bl == bl - 1) RSV_HIP(flush(i - 1));
     }
-    if (acc && n_sweeps > 0)  // the state after the last sweep
+    if (acc && n_sweeps > 0) {  // the state after the last sweep, and its batch
         RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
-                                  c->h_prop, level_moves(c) ? c->shift : nullptr,
-                                  batch_row(n_sweeps - 1), trace->h_sq_sum, c->pb.precision));
+                                  c->h_prop, level_moves(c) ? c->shift : nullptr, acc_sum_f,
+                                  acc_sq_f, c->pb.precision));
+        RSV_HIP(flush(n_sweeps - 1));
+    }
     return settle(c);
 }
 

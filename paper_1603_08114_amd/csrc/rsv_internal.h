@@ -72,8 +72,8 @@ struct TrajArgs {
     double jitter;              // step-size jitter j (0: fixed dtau)
     const double* shift;        // per chain: pending level shift of the current
                                 // state (value = stored + shift), or nullptr
-    double* acc_sum;            // per state entry: add the state the trajectory
-    double* acc_sq;             // starts from, and its square (or nullptr)
+    float* acc_sum;             // per state entry: add the state the trajectory
+    float* acc_sq;              // starts from, and its square (or nullptr)
     int32_t terms;
 };
 
@@ -135,11 +135,16 @@ hipError_t launch_resident(hipStream_t st, int precision, int S, bool mass, cons
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,
                                const void* h_b, const double* shift, void* h_dst, int precision);
-// Add every chain's current state to batch_sum (and its square to sq_sum).
+// Add every chain's current state to batch_sum (and its square to sq_sum):
+// the FP32 per-batch accumulators of the per-kernel sweep path.
 hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                              int32_t max_T, const int32_t* state_sel, const void* h_a,
-                             const void* h_b, const double* shift, double* batch_sum,
-                             double* sq_sum, int precision);
+                             const void* h_b, const double* shift, float* batch_sum,
+                             float* sq_sum, int precision);
+// batch_sum[i] += acc_sum[i], sq_sum[i] += acc_sq[i] (each may be nullptr),
+// then acc_sum = acc_sq = 0, for i < n.
+hipError_t launch_flush(hipStream_t st, int64_t n, float* acc_sum, float* acc_sq,
+                        double* batch_sum, double* sq_sum);
 // Leave every chain's current state (including a pending level shift) in h_a;
 // clear state_sel and the shifts.
 hipError_t launch_settle(hipStream_t st, const ChainDesc* chains, int32_t n_chains, int32_t max_T,

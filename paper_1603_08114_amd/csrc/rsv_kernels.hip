@@ -137,10 +137,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         for (int j = 0; j < S; ++j) {
             const int t = t0 + j;
             if (t >= td.a && t < td.b) {
-                const double v = static_cast<double>(h[j]);
+                const float v = static_cast<float>(h[j]);
                 const int64_t i = cd.h_off + t;
                 if (A.acc_sum) A.acc_sum[i] += v;
-                if (A.acc_sq) A.acc_sq[i] = __builtin_fma(v, v, A.acc_sq[i]);
+                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, A.acc_sq[i]);
             }
         }
     }
@@ -831,7 +831,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_accumulate(const ChainDesc* chains,
                                                     const int32_t* state_sel, const R* h_a,
                                                     const R* h_b, const double* shift,
-                                                    double* batch_sum, double* sq_sum) {
+                                                    float* batch_sum, float* sq_sum) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
     const R* src = (state_sel[c] ? h_b : h_a) + cd.h_off;
@@ -840,9 +840,21 @@ __global__ __launch_bounds__(256) void k_accumulate(const ChainDesc* chains,
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < cd.T;
          t += stride) {
         const int64_t i = cd.h_off + t;
-        const double v = static_cast<double>(state_at(src, t, sft));
+        const float v = static_cast<float>(state_at(src, t, sft));
         if (batch_sum) batch_sum[i] += v;
-        if (sq_sum) sq_sum[i] = __builtin_fma(v, v, sq_sum[i]);
+        if (sq_sum) sq_sum[i] = __builtin_fmaf(v, v, sq_sum[i]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_flush(int64_t n, float* acc_sum, float* acc_sq,
+                                               double* batch_sum, double* sq_sum) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += stride) {
+        if (batch_sum) batch_sum[i] += static_cast<double>(acc_sum[i]);
+        if (sq_sum) sq_sum[i] += static_cast<double>(acc_sq[i]);
+        acc_sum[i] = 0.0f;
+        acc_sq[i] = 0.0f;
     }
 }
 
@@ -1079,10 +1091,18 @@ hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t 
     return hipGetLastError();
 }
 
+hipError_t launch_flush(hipStream_t st, int64_t n, float* acc_sum, float* acc_sq,
+                        double* batch_sum, double* sq_sum) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flush, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, acc_sum,
+                       acc_sq, batch_sum, sq_sum);
+    return hipGetLastError();
+}
+
 hipError_t launch_accumulate(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                              int32_t max_T, const int32_t* state_sel, const void* h_a,
-                             const void* h_b, const double* shift, double* batch_sum,
-                             double* sq_sum, int precision) {
+                             const void* h_b, const double* shift, float* batch_sum,
+                             float* sq_sum, int precision) {
     const dim3 g(grid_for(max_T, 256, 1024), n_chains), b(256);
     if (precision == RSV_F64)
         hipLaunchKernelGGL(k_accumulate<double>, g, b, 0, st, chains, state_sel,

@@ -411,16 +411,20 @@ def test_batch_mean_accumulators_match_recorded_trace(Ts, flags):
     out = smp.sweep(0, n, (k, dt), update_theta=True, record=(), record_h=True, batch_len=bl)
     h = out["h"].cpu().numpy()
     bs = out["h_batch_sum"].cpu().numpy()
+    resident = flags == 0 and max(Ts) <= 1024  # one 4 x 4 tile per chain (FP64 default)
+    # resident sweeps add every state in FP64 (the squares with one FMA
+    # rounding); per-kernel sweeps sum a batch in FP32 first
+    tol = 0.0 if resident else 4e-7 * bl * np.abs(h).max()
     for b in range(bs.shape[0]):
         ref = np.zeros(h.shape[1])
         for i in range(b * bl, min(n, (b + 1) * bl)):
             ref += h[i]
-        np.testing.assert_array_equal(bs[b], ref)
+        np.testing.assert_allclose(bs[b], ref, rtol=0, atol=tol)
     sq = np.zeros(h.shape[1])
     for i in range(n):
         sq += h[i] * h[i]
-    # the device forms v*v + sum with one FMA rounding
-    np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq, rtol=1e-14)
+    np.testing.assert_allclose(out["h_sq_sum"].cpu().numpy(), sq,
+                               rtol=1e-14 if resident else 4e-7 * n)
 
 
 @pytest.mark.parametrize("precision,dtau_jitter,flags", [(RSV_F64, 0.0, 0), (RSV_F32_MIXED, 0.0, 0),
@@ -444,9 +448,11 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision, dtau_jitter, flags):
         o["state"] = smp.h.clone()
         o["theta_final"] = smp.theta.clone()
         outs.append(o)
-    for key in ("delta_h", "accepted", "theta", "h", "h_batch_sum", "h_sq_sum", "state",
-                "theta_final"):
+    for key in ("delta_h", "accepted", "theta", "h", "state", "theta_final"):
         assert torch.equal(outs[0][key], outs[1][key]), key
+    # the per-kernel path sums each batch in FP32 before adding it
+    for key in ("h_batch_sum", "h_sq_sum"):
+        torch.testing.assert_close(outs[0][key], outs[1][key], rtol=4e-7 * n, atol=1e-5)
     assert outs[0]["accepted"].float().mean() > 0.3
 
 
