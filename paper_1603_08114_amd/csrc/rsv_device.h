@@ -74,13 +74,14 @@ __device__ inline void gauss_pair(double u0, double u1, double& z0, double& z1) 
 
 // ---------------------------------------------------------------------------
 // Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  The lane at the
-// end that has no source receives 0.
+// end that has no source receives 0 through the bound control bit, so the
+// destination needs no initial value.
 // ---------------------------------------------------------------------------
 __device__ inline int dpp_from_lower(int v) {  // lane l <- lane l-1
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
 }
 __device__ inline int dpp_from_upper(int v) {  // lane l <- lane l+1
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
 }
 
 __device__ inline float from_lower(float v) {
@@ -99,6 +100,23 @@ __device__ inline double from_upper(double v) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
     const uint32_t lo = static_cast<uint32_t>(dpp_from_upper(static_cast<int>(b)));
     const uint32_t hi = static_cast<uint32_t>(dpp_from_upper(static_cast<int>(b >> 32)));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
+// Values that are equal on every active lane of the wavefront (per-tile
+// constants), moved to scalar registers: the loop then reads them as scalar
+// operands instead of holding a copy in every lane.
+// ---------------------------------------------------------------------------
+__device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float wave_uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ inline double wave_uniform(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(b)));
+    const uint32_t hi =
+        static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32)));
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 

@@ -8,6 +8,8 @@
 // of each lane with its neighbours by DPP lane shifts, and runs all k steps
 // without touching HBM.  Sites within k+1 of a tile's cut are recomputed by
 // the neighbouring tile (halo), so every exact site is produced once.
+#include <type_traits>
+
 #include "rsv_device.h"
 #include "rsv_exp.h"
 #include "rsv_internal.h"
@@ -196,48 +198,81 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 
     // ---- leapfrog, eqs. (6)-(8); adjacent h half steps of consecutive
     //      steps are merged into one full step ----
-    const R dt_r = static_cast<R>(dt);
-    const R half_r = static_cast<R>(0.5 * dt);
+    // Per-tile constants live in scalar registers.
+    const R s_dt = wave_uniform(static_cast<R>(dt));
+    const R s_half = wave_uniform(static_cast<R>(0.5 * dt));
+    const R s_mda = wave_uniform(mda), s_db = wave_uniform(db);
+    const R s_mu = wave_uniform(mu_r), s_phi = wave_uniform(phi_r);
+    const int n_steps = wave_uniform(cd.n_steps);
 #pragma unroll
     for (int j = 0; j < S; ++j)
-        h[j] += (MASS ? R(0.5) * dtm[MASS ? j : 0] : half_r) * p[j];
+        h[j] += (MASS ? R(0.5) * dtm[MASS ? j : 0] : s_half) * p[j];
 
     const bool lane_first = (t0 == 0);
     const bool lane_last = (t0 + S == T);
-    for (int step = 0; step < cd.n_steps; ++step) {
+    // only the wavefronts that hold a chain end substitute a neighbour
+    const bool wave_end = __ballot(lane_first || lane_last) != 0;
+    // p += dt * force(h); `par` selects the LDS slots of this step, which
+    // alternate with the step index (a wavefront one step ahead writes the
+    // other slot while its neighbours still read this one)
+    auto kick = [&](auto par_c) {
+        constexpr int par = decltype(par_c)::value;
         R hl0 = from_lower(h[S - 1]);
         R hrS = from_upper(h[0]);
         if constexpr (NW > 1) {
-            const int par = step & 1;
             if (lane == 0) sh.left[par][wv] = h[0];
             if (lane == kWave - 1) sh.right[par][wv] = h[S - 1];
             __syncthreads();
             if (lane == 0 && wv > 0) hl0 = sh.right[par][wv - 1];
             if (lane == kWave - 1 && wv < NW - 1) hrS = sh.left[par][wv + 1];
         }
-        if (lane_first) hl0 = ghost_neighbour(h[0], mu_r, phi_r);
-        if (lane_last) hrS = ghost_neighbour(h[S - 1], mu_r, phi_r);
+        if (wave_end) {
+            // a real branch: without the barrier the compiler computes the
+            // substitutes in every wavefront and selects
+            asm volatile("" ::: "memory");
+            if (lane_first) hl0 = ghost_neighbour(h[0], s_mu, s_phi);
+            if (lane_last) hrS = ghost_neighbour(h[S - 1], s_mu, s_phi);
+        }
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const R hl = (j == 0) ? hl0 : h[j - 1];
             R hr = (j == S - 1) ? hrS : h[j + 1];
             if constexpr (EDGE) {
-                if (j < S - 1 && t0 + j == T - 1) hr = ghost_neighbour(h[j], mu_r, phi_r);
+                if (j < S - 1 && t0 + j == T - 1) hr = ghost_neighbour(h[j], s_mu, s_phi);
             }
             R acc = p[j] + dc[j];
-            acc += mda * h[j];
-            acc += db * (hl + hr);
+            acc += s_mda * h[j];
+            acc += s_db * (hl + hr);
             if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
             p[j] = acc;
         }
-        const bool last = (step + 1 == cd.n_steps);
+    };
+    // h += dt p, or the closing half step dt/2 p after the last kick
+    auto drift = [&](auto last_c) {
+        constexpr bool last = decltype(last_c)::value;
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const R c = MASS ? (last ? R(0.5) * dtm[MASS ? j : 0] : dtm[MASS ? j : 0])
-                             : (last ? half_r : dt_r);
+                             : (last ? s_half : s_dt);
             h[j] += c * p[j];
         }
+    };
+    using Even = std::integral_constant<int, 0>;
+    using Odd = std::integral_constant<int, 1>;
+    int step = 0;
+    for (; step + 2 < n_steps; step += 2) {
+        kick(Even{});
+        drift(std::false_type{});
+        kick(Odd{});
+        drift(std::false_type{});
     }
+    // one or two steps remain; `step` is even
+    kick(Even{});
+    if (n_steps - step == 2) {
+        drift(std::false_type{});
+        kick(Odd{});
+    }
+    drift(std::true_type{});
 
     // ---- dH = sum over exact sites of per-site differences (FP64), and the
     //      sufficient statistics of the proposal and of the current state ----
@@ -383,7 +418,8 @@ __device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
 
 // Identity mass.
 template <typename R, int S, int NW, bool RET>
-__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void k_traj(TrajArgs<R> A) {
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW)
+void k_traj(TrajArgs<R> A) {
     traj_launch_body<R, S, NW, false, RET>(A);
 }
 

@@ -54,6 +54,12 @@ def descriptor(asm: str, name: str) -> dict:
 
 
 def leapfrog_loop(text: str, n_dpp: int):
+    """Instruction counts of the innermost loop that carries the lane shifts.
+
+    The loop runs two leapfrog steps per iteration.  Blocks that hold the
+    chain-end substitution (marked by an empty inline-asm statement, skipped
+    by a uniform branch in every wavefront without a chain end) are left out:
+    the count is the path almost every wavefront takes."""
     lines = [l.strip() for l in text.split("\n")]
     labels = {}
     for i, l in enumerate(lines):
@@ -64,13 +70,20 @@ def leapfrog_loop(text: str, n_dpp: int):
     for i, l in enumerate(lines):
         m = re.match(r"s_cbranch_\w+ (\.LBB\w+)|s_branch (\.LBB\w+)", l)
         tgt = m and (m.group(1) or m.group(2))
-        if tgt in labels and labels[tgt] < i:
-            seg = [x for x in lines[labels[tgt]:i + 1]
-                   if x and not x.startswith((";", ".")) and not x.endswith(":")]
-            # the innermost loop that carries one step's lane shifts
+        if tgt in labels and labels[tgt] < i and "Loop Header" in lines[labels[tgt]]:
+            seg = lines[labels[tgt]:i + 1]
             if sum("_dpp" in x for x in seg) >= n_dpp and (best is None or len(seg) < len(best)):
                 best = seg
-    return Counter(x.split()[0] for x in best)
+    blocks, cur = [], []
+    for x in best:
+        if re.match(r"^(\.LBB\w+:|; %bb\.\d+:)", x):  # named and fall-through blocks
+            blocks.append(cur)
+            cur = []
+        cur.append(x)
+    blocks.append(cur)
+    kept = [x for b in blocks if not any("ASMSTART" in y for y in b) for x in b
+            if x and not x.startswith((";", ".")) and not x.endswith(":")]
+    return Counter(x.split()[0] for x in kept)
 
 
 def count(asm: str) -> dict:
