@@ -58,11 +58,13 @@ def _load():
         "orc_hamiltonian": (C.c_double, [_I64, _D, _D, _D, _D, _D, P(Theta), C.c_int]),
         "orc_leapfrog": (None, [_I64, _D, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
                                 C.c_double]),
+        "orc_omelyan": (None, [_I64, _D, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
+                               C.c_double]),
         "orc_delta_h": (C.c_double, [_I64, _D, _D, _D, _D, _D, _D, _D, P(Theta), C.c_int]),
         "orc_momenta": (None, [_U64, _U64, _U64, _I64, _D, _D]),
         "orc_log_u": (C.c_double, [_U64, _U64, _U64]),
         "orc_trajectory": (C.c_int, [_I64, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
-                                     C.c_double, _U64, _U64, _U64, _D, _D, _D, _D]),
+                                     C.c_double, C.c_int, _U64, _U64, _U64, _D, _D, _D, _D]),
         "orc_suffstats": (None, [_I64, _D, _D, C.c_double, C.c_double, _D]),
         "orc_theta_update": (C.c_int, [_I64, _D, P(Theta), P(Prior), C.c_int, _U64, _U64,
                                        _U64, P(Theta)]),
@@ -75,7 +77,8 @@ def _load():
         "orc_level_move": (C.c_int, [_I64, _D, P(Theta), _D, P(Prior), C.c_int, _U64, _U64,
                                      _U64, _D]),
         "orc_run": (_I64, [_I64, _D, P(Theta), _D, _D, _D, P(Prior), C.c_int, C.c_int32,
-                           C.c_double, C.c_double, C.c_int, _U64, _U64, _U64, _I64, C.c_int, _D,
+                           C.c_double, C.c_double, C.c_int, C.c_int, _U64, _U64, _U64, _I64,
+                           C.c_int, _D,
                            P(C.c_int32), P(Theta), _D]),
     }
     for name, (res, args) in sig.items():
@@ -173,6 +176,22 @@ def leapfrog(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
     return h, p
 
 
+INT_LEAPFROG = 0
+INT_OMELYAN = 1
+OMELYAN_LAMBDA = 0.1931833275037836
+
+
+def omelyan(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
+    """k steps of Omelyan's second-order minimum-norm scheme (h first);
+    returns new (h, p) (inputs untouched)."""
+    h = _arr(h).copy(); T = h.size
+    p = _arr(p, T).copy()
+    lm = None if log_m is None else _arr(log_m, T)
+    _lib.orc_omelyan(T, _ptr(h), _ptr(p), _ptr(lm), _ptr(_arr(y2, T)), _ptr(_arr(r, T)),
+                     C.byref(theta_struct(theta)), terms, int(k), float(dtau))
+    return h, p
+
+
 def delta_h(h0, p0, h1, p1, y2, r, theta, terms=TERMS_RSV, log_m=None):
     h0 = _arr(h0); T = h0.size
     lm = None if log_m is None else _arr(log_m, T)
@@ -198,7 +217,7 @@ def step_size(seed, sweep, chain, dtau, jitter):
 
 
 def trajectory(h, y2, r, theta, k, dtau, seed=0, sweep=0, chain=0, terms=TERMS_RSV,
-               p0=None, log_u=None, log_m=None, jitter=0.0):
+               p0=None, log_u=None, log_m=None, jitter=0.0, integrator=INT_LEAPFROG):
     """One HMC trajectory.  Returns dict(h, accepted, dH, p0)."""
     dtau = step_size(seed, sweep, chain, dtau, jitter)
     h = _arr(h).copy(); T = h.size
@@ -209,7 +228,8 @@ def trajectory(h, y2, r, theta, k, dtau, seed=0, sweep=0, chain=0, terms=TERMS_R
     dH = np.zeros(1)
     acc = _lib.orc_trajectory(T, _ptr(h), _ptr(lm), _ptr(_arr(y2, T)), _ptr(_arr(r, T)),
                               C.byref(theta_struct(theta)), terms, int(k), float(dtau),
-                              seed, sweep, chain, _ptr(p0a), _ptr(lu), _ptr(p_used), _ptr(dH))
+                              int(integrator), seed, sweep, chain, _ptr(p0a), _ptr(lu),
+                              _ptr(p_used), _ptr(dH))
     return dict(h=h, accepted=bool(acc), dH=float(dH[0]), p0=p_used)
 
 
@@ -269,7 +289,7 @@ def neumaier_sum(x):
 
 def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
         update_theta=True, prior=None, terms=TERMS_RSV, log_m=None, keep_h=False, jitter=0.0,
-        moves=0):
+        moves=0, integrator=INT_LEAPFROG):
     """n sweeps of one chain.  Returns dict with final h/theta and traces."""
     h = _arr(h).copy(); T = h.size
     th = theta_struct(theta)
@@ -281,7 +301,8 @@ def run(h, theta, y2, r, k, dtau, n_sweeps, seed=0, chain=0, first_sweep=0,
     htrace = np.zeros((n_sweeps, T)) if keep_h else None
     n_acc = _lib.orc_run(T, _ptr(h), C.byref(th), _ptr(lm), _ptr(_arr(y2, T)),
                          _ptr(_arr(r, T)), C.byref(prior_struct(prior)), terms, int(k),
-                         float(dtau), float(jitter), int(moves), seed, chain, first_sweep,
+                         float(dtau), float(jitter), int(moves), int(integrator), seed, chain,
+                         first_sweep,
                          n_sweeps, int(update_theta),
                          _ptr(dH), acc.ctypes.data_as(C.POINTER(C.c_int32)), ttrace,
                          _ptr(htrace))

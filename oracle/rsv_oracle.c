@@ -206,6 +206,45 @@ void orc_leapfrog(int64_t T, double *h, double *p, const double *log_m,
     free(g);
 }
 
+/* Omelyan's second-order minimum-norm integrator (Omelyan, Mryglod and
+ * Folk, Comput. Phys. Commun. 151 (2003) 272; its h-first form is the one
+ * Takaishi and de Forcrand tested for HMC, Phys. Rev. E 73 (2006) 036706),
+ * a higher-order alternative to the leapfrog that Sec. 3 says may be used.
+ * Each of the k steps: h by lambda dtau, p by dtau/2, h by (1 - 2 lambda)
+ * dtau, p by dtau/2, h by lambda dtau, with the momentum steps taking the
+ * force at the current h.  Two force evaluations per step. */
+void orc_omelyan(int64_t T, double *h, double *p, const double *log_m,
+                 const double *y2, const double *r, const orc_theta *th, int terms,
+                 int32_t k, double dtau)
+{
+    const double lambda = ORC_OMELYAN_LAMBDA;
+    double *g = (double *)malloc((size_t)T * sizeof(double));
+    double *inv_m = (double *)malloc((size_t)T * sizeof(double));
+    for (int64_t t = 0; t < T; ++t) inv_m[t] = log_m ? exp(-log_m[t]) : 1.0;
+    for (int32_t step = 0; step < k; ++step) {
+        for (int64_t t = 0; t < T; ++t) h[t] = h[t] + lambda * dtau * p[t] * inv_m[t];
+        orc_grad(T, h, y2, r, th, terms, g);
+        for (int64_t t = 0; t < T; ++t) p[t] = p[t] - 0.5 * dtau * g[t];
+        for (int64_t t = 0; t < T; ++t)
+            h[t] = h[t] + (1.0 - 2.0 * lambda) * dtau * p[t] * inv_m[t];
+        orc_grad(T, h, y2, r, th, terms, g);
+        for (int64_t t = 0; t < T; ++t) p[t] = p[t] - 0.5 * dtau * g[t];
+        for (int64_t t = 0; t < T; ++t) h[t] = h[t] + lambda * dtau * p[t] * inv_m[t];
+    }
+    free(inv_m);
+    free(g);
+}
+
+void orc_integrate(int64_t T, double *h, double *p, const double *log_m,
+                   const double *y2, const double *r, const orc_theta *th, int terms,
+                   int32_t k, double dtau, int integrator)
+{
+    if (integrator == ORC_INT_OMELYAN)
+        orc_omelyan(T, h, p, log_m, y2, r, th, terms, k, dtau);
+    else
+        orc_leapfrog(T, h, p, log_m, y2, r, th, terms, k, dtau);
+}
+
 /* dH as a sum of per-site changes, each formed from differences so that
  * nothing of the size of H itself is ever subtracted:
  *   x'^2 - x^2 = (x'-x)(x'+x);  e^{-h'} - e^{-h} = e^{-h} expm1(-(h'-h)). */
@@ -275,8 +314,9 @@ double orc_step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau,
 
 int orc_trajectory(int64_t T, double *h, const double *log_m,
                    const double *y2, const double *r, const orc_theta *th, int terms,
-                   int32_t k, double dtau, uint64_t seed, uint64_t sweep, uint64_t chain,
-                   const double *p0, const double *log_u, double *p_out, double *dH_out)
+                   int32_t k, double dtau, int integrator, uint64_t seed, uint64_t sweep,
+                   uint64_t chain, const double *p0, const double *log_u, double *p_out,
+                   double *dH_out)
 {
     size_t bytes = (size_t)T * sizeof(double);
     double *h_start = (double *)malloc(bytes);
@@ -288,7 +328,7 @@ int orc_trajectory(int64_t T, double *h, const double *log_m,
     memcpy(p, p_start, bytes);
     if (p_out) memcpy(p_out, p_start, bytes);
 
-    orc_leapfrog(T, h, p, log_m, y2, r, th, terms, k, dtau);
+    orc_integrate(T, h, p, log_m, y2, r, th, terms, k, dtau, integrator);
     double dH = orc_delta_h(T, h_start, p_start, h, p, log_m, y2, r, th, terms);
     double lu = log_u ? *log_u : orc_log_u(seed, sweep, chain);
     /* accept with probability min{1, exp(-dH)}: u < exp(-dH); ties and
@@ -500,18 +540,18 @@ int orc_level_move(int64_t T, double *h, orc_theta *th, const double *y2, const 
 
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, double jitter, int moves, uint64_t seed,
-                uint64_t chain, uint64_t first_sweep, int64_t n_sweeps, int update_theta,
-                double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
-                double *h_trace)
+                int32_t k, double dtau, double jitter, int moves, int integrator,
+                uint64_t seed, uint64_t chain, uint64_t first_sweep, int64_t n_sweeps,
+                int update_theta, double *dH_trace, int32_t *acc_trace,
+                orc_theta *theta_trace, double *h_trace)
 {
     int64_t n_acc = 0;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         uint64_t sweep = first_sweep + (uint64_t)i;
         double dH;
         double dt = orc_step_size(seed, sweep, chain, dtau, jitter);
-        int acc = orc_trajectory(T, h, log_m, y2, r, th, terms, k, dt, seed, sweep, chain,
-                                 NULL, NULL, NULL, &dH);
+        int acc = orc_trajectory(T, h, log_m, y2, r, th, terms, k, dt, integrator, seed,
+                                 sweep, chain, NULL, NULL, NULL, &dH);
         n_acc += acc;
         if (update_theta) {
             if (moves & ORC_MOVE_LEVEL)

@@ -75,6 +75,18 @@ double orc_hamiltonian(int64_t T, const double *h, const double *p, const double
 void orc_leapfrog(int64_t T, double *h, double *p, const double *log_m,
                   const double *y2, const double *r, const orc_theta *th, int terms,
                   int32_t k, double dtau);
+/* Integrators of the trajectory: the paper's leapfrog, or Omelyan's
+ * second-order minimum-norm scheme (h-first form, lambda below). */
+enum { ORC_INT_LEAPFROG = 0, ORC_INT_OMELYAN = 1 };
+#define ORC_OMELYAN_LAMBDA 0.1931833275037836
+/* k steps of the Omelyan scheme, in place (2k force evaluations). */
+void orc_omelyan(int64_t T, double *h, double *p, const double *log_m,
+                 const double *y2, const double *r, const orc_theta *th, int terms,
+                 int32_t k, double dtau);
+/* k steps of the integrator `integrator` (ORC_INT_*), in place. */
+void orc_integrate(int64_t T, double *h, double *p, const double *log_m,
+                   const double *y2, const double *r, const orc_theta *th, int terms,
+                   int32_t k, double dtau, int integrator);
 /* dH = H(h1,p1) - H(h0,p0) as a compensated sum of per-site differences. */
 double orc_delta_h(int64_t T, const double *h0, const double *p0,
                    const double *h1, const double *p1, const double *log_m,
@@ -90,13 +102,15 @@ double orc_log_u(uint64_t seed, uint64_t sweep, uint64_t chain);
  * (an extension: the paper's dtau is fixed; j = 0 returns dtau). */
 double orc_step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau, double jitter);
 
-/* One HMC trajectory on h (in place: left at h' if accepted, else at h0).
+/* One HMC trajectory on h (in place: left at h' if accepted, else at h0)
+ * with k steps of the integrator `integrator` (ORC_INT_*).
  * p0 / log_u may be NULL (then drawn from the streams).  p_out (may be NULL)
  * receives the momenta used.  Returns 1 if accepted, 0 if rejected. */
 int orc_trajectory(int64_t T, double *h, const double *log_m,
                    const double *y2, const double *r, const orc_theta *th, int terms,
-                   int32_t k, double dtau, uint64_t seed, uint64_t sweep, uint64_t chain,
-                   const double *p0, const double *log_u, double *p_out, double *dH_out);
+                   int32_t k, double dtau, int integrator, uint64_t seed, uint64_t sweep,
+                   uint64_t chain, const double *p0, const double *log_u, double *p_out,
+                   double *dH_out);
 
 /* Sufficient statistics of h for the theta update with shifts c_mu, c_xi:
  * out = {B, B2, BB, D1, D2, b_first, b_last}. */
@@ -149,10 +163,10 @@ int orc_level_move(int64_t T, double *h, orc_theta *th, const double *y2, const 
  * h_trace[n*T] (h after each sweep).  Returns the number accepted. */
 int64_t orc_run(int64_t T, double *h, orc_theta *th, const double *log_m,
                 const double *y2, const double *r, const orc_prior *pr, int terms,
-                int32_t k, double dtau, double jitter, int moves, uint64_t seed,
-                uint64_t chain, uint64_t first_sweep, int64_t n_sweeps, int update_theta,
-                double *dH_trace, int32_t *acc_trace, orc_theta *theta_trace,
-                double *h_trace);
+                int32_t k, double dtau, double jitter, int moves, int integrator,
+                uint64_t seed, uint64_t chain, uint64_t first_sweep, int64_t n_sweeps,
+                int update_theta, double *dH_trace, int32_t *acc_trace,
+                orc_theta *theta_trace, double *h_trace);
 
 #ifdef __cplusplus
 }
