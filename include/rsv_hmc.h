@@ -82,8 +82,17 @@ enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
  *   tag 4, block 0 (Box-Muller z from u0, u1; u2 the test), Gamma attempts
  *   in blocks 1..32.  An extension: the paper's method updates h only, and
  *   the Gibbs theta step alone mixes slowly along this direction (xi + h_t is
- *   pinned by ln RV_t).  Off by default. */
-enum { RSV_FLAG_NO_RESIDENT = 1, RSV_FLAG_LEVEL_MOVE = 2 };
+ *   pinned by ln RV_t).  Off by default.
+ * RSV_FLAG_OMELYAN: the trajectory integrates with Omelyan's second-order
+ *   minimum-norm scheme instead of the leapfrog of eqs. (6)-(8) (Sec. 3
+ *   allows higher-order integrators): each of the n_steps steps moves h by
+ *   lambda dtau, p by dtau/2, h by (1 - 2 lambda) dtau, p by dtau/2, h by
+ *   lambda dtau (lambda = 0.1931833275037836; Omelyan, Mryglod and Folk,
+ *   Comput. Phys. Commun. 151 (2003) 272).  Two force evaluations per step,
+ *   so a step costs about twice a leapfrog step and the halo of a tile is
+ *   sized for 2 n_steps (max_steps is checked against that).  Off by
+ *   default. */
+enum { RSV_FLAG_NO_RESIDENT = 1, RSV_FLAG_LEVEL_MOVE = 2, RSV_FLAG_OMELYAN = 4 };
 
 /* theta of Sec. 2. */
 typedef struct { double phi, mu, xi, sig2_eta, sig2_u; } rsv_theta;

@@ -50,16 +50,23 @@ rsv_status fail(rsv_status code, const char* fmt, ...) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-int halo_for(int n_steps) { return (n_steps + 1 + 3) & ~3; }
+// Each momentum step (kick) invalidates one more site at each tile cut: the
+// halo covers the kicks of a trajectory plus the bond to the next site.
+int halo_for(int n_kicks) { return (n_kicks + 1 + 3) & ~3; }
+
+// Kicks per trajectory of n_steps: one per leapfrog step, two per Omelyan step.
+int kicks_for(int32_t flags, int n_steps) {
+    return (flags & RSV_FLAG_OMELYAN) ? 2 * n_steps : n_steps;
+}
 
 // Tile decomposition of one chain of length T for tiles of NW wavefronts
-// with S sites per lane and a trajectory of n_steps: tiles of 64*NW*S loaded
+// with S sites per lane and a trajectory of n_kicks: tiles of 64*NW*S loaded
 // sites whose exact ranges [a, b) partition [0, T).  Returns false if the
 // halo does not fit.
-bool tile_chain(int32_t chain, int32_t T, int S, int NW, int n_steps,
+bool tile_chain(int32_t chain, int32_t T, int S, int NW, int n_kicks,
                 std::vector<TileDesc>& body, std::vector<TileDesc>& edges) {
     const int L = 64 * NW * S;
-    const int H = halo_for(n_steps);
+    const int H = halo_for(n_kicks);
     if (T <= L) {
         const TileDesc t{chain, 0, 0, T, T % S != 0 ? 1 : 0, {0, 0, 0}};
         if (t.edge) edges.push_back(t); else body.push_back(t);
@@ -81,9 +88,9 @@ bool tile_chain(int32_t chain, int32_t T, int S, int NW, int n_steps,
     }
 }
 
-int32_t count_tiles(int32_t T, int S, int NW, int n_steps) {
+int32_t count_tiles(int32_t T, int S, int NW, int n_kicks) {
     std::vector<TileDesc> b, e;
-    if (!tile_chain(0, T, S, NW, n_steps, b, e)) return -1;
+    if (!tile_chain(0, T, S, NW, n_kicks, b, e)) return -1;
     return static_cast<int32_t>(b.size() + e.size());
 }
 
@@ -114,7 +121,7 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
     if (!(pb->dtau_jitter >= 0.0 && pb->dtau_jitter < 1.0))
         return fail(RSV_EINVAL, "dtau_jitter must be in [0, 1)");
-    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE))
+    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE | RSV_FLAG_OMELYAN))
         return fail(RSV_EINVAL, "unknown flags 0x%x", pb->flags);
     const rsv_prior& p = pb->prior;
     if (!(p.mu_var > 0 && p.xi_var > 0 && p.eta_shape > 0 && p.eta_scale > 0 && p.u_shape > 0 &&
@@ -146,7 +153,7 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     int64_t tiles = 0;
     for (int s = 0; s < pb->n_series; ++s) {
         const int32_t T = static_cast<int32_t>(pb->offsets[s + 1] - pb->offsets[s]);
-        const int32_t n = count_tiles(T, S, NW, pb->max_steps);
+        const int32_t n = count_tiles(T, S, NW, kicks_for(pb->flags, pb->max_steps));
         if (n < 0)
             return fail(RSV_EINVAL, "max_steps = %d needs a halo wider than a tile (%d sites)",
                         pb->max_steps, 64 * NW * S);
@@ -253,7 +260,8 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
             d.series = s;
             d.tile_begin = static_cast<int32_t>(body.size());
             const size_t n_edge_before = edges.size();
-            if (!tile_chain(ch, T, c->S, c->NW, lf[s].n_steps, body, edges))
+            if (!tile_chain(ch, T, c->S, c->NW, kicks_for(c->pb.flags, lf[s].n_steps), body,
+                            edges))
                 return fail(RSV_EINVAL, "series %d: n_steps %d too large for a tile", s,
                             lf[s].n_steps);
             d.tile_count = static_cast<int32_t>(body.size()) - d.tile_begin;
@@ -330,6 +338,7 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.acc_sum = nullptr;
     a.acc_sq = nullptr;
     a.terms = c->pb.terms;
+    a.omelyan = (c->pb.flags & RSV_FLAG_OMELYAN) ? 1 : 0;
     return a;
 }
 

@@ -75,6 +75,7 @@ struct TrajArgs {
     float* acc_sum;             // per state entry: add the state the trajectory
     float* acc_sq;              // starts from, and its square (or nullptr)
     int32_t terms;
+    int32_t omelyan;            // 1: Omelyan's integrator (2 kicks per step)
 };
 
 struct FinalizeArgs {

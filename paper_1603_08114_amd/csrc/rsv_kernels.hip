@@ -97,12 +97,14 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const double inv_se = 1.0 / th.sig2_eta;
     const double inv_su = rv ? 1.0 / th.sig2_u : 0.0;
     const double dt = step_size(A.seed, A.sweep, static_cast<uint64_t>(td.chain), cd.dtau, A.jitter);
+    // momentum steps: dt (leapfrog) or dt/2 (Omelyan: two per step)
+    const double dk = A.omelyan ? 0.5 * dt : dt;
     // force g_t = c_t + alpha h_t - beta (h_{t-1} + h_{t+1}) - s_t e^{-h_t} / 2
     const double alpha = (1.0 + phi * phi) * inv_se + inv_su;
     const double beta = phi * inv_se;
     const double c_base = (RET ? 0.5 : 0.0) + xi * inv_su - mu * (1.0 - phi) * (1.0 - phi) * inv_se;
-    const R mda = static_cast<R>(-dt * alpha);
-    const R db = static_cast<R>(dt * beta);
+    const R mda = static_cast<R>(-dk * alpha);
+    const R db = static_cast<R>(dk * beta);
     const R mu_r = static_cast<R>(mu), phi_r = static_cast<R>(phi);
 
     R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1];
@@ -121,8 +123,8 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         h[j] = live ? state_at(hc, t, shift) : R(0);
         const double yy = live ? static_cast<double>(y2[t]) : 0.0;
         const double rr = live ? static_cast<double>(lr[t]) : 0.0;
-        dc[j] = static_cast<R>(-dt * (c_base - rr * inv_su));
-        ds[j] = RET ? static_cast<R>(0.5 * dt * yy) : R(0);
+        dc[j] = static_cast<R>(-dk * (c_base - rr * inv_su));
+        ds[j] = RET ? static_cast<R>(0.5 * dk * yy) : R(0);
         if constexpr (STAGE) {
             constexpr int NT = 64 * NW;
             const int g = wv * kWave + lane;
@@ -196,24 +198,23 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
-    // ---- leapfrog, eqs. (6)-(8); adjacent h half steps of consecutive
-    //      steps are merged into one full step ----
+    // ---- integrator: the leapfrog of eqs. (6)-(8), or Omelyan's scheme ----
+    // Both are a chain of momentum steps (kicks) p += dk * force(h), all
+    // alike, with position steps (drifts) h += c dt p / m between them:
+    //   leapfrog, k kicks:  c = 1/2, then 1 between kicks, 1/2 at the end
+    //                       (adjacent half steps of consecutive steps merged);
+    //   Omelyan, 2k kicks:  c = lambda, then 1 - 2 lambda and 2 lambda in
+    //                       turn, lambda at the end.
     // Per-tile constants live in scalar registers.
-    const R s_dt = wave_uniform(static_cast<R>(dt));
-    const R s_half = wave_uniform(static_cast<R>(0.5 * dt));
     const R s_mda = wave_uniform(mda), s_db = wave_uniform(db);
     const R s_mu = wave_uniform(mu_r), s_phi = wave_uniform(phi_r);
     const int n_steps = wave_uniform(cd.n_steps);
-#pragma unroll
-    for (int j = 0; j < S; ++j)
-        h[j] += (MASS ? R(0.5) * dtm[MASS ? j : 0] : s_half) * p[j];
-
     const bool lane_first = (t0 == 0);
     const bool lane_last = (t0 + S == T);
     // only the wavefronts that hold a chain end substitute a neighbour
     const bool wave_end = __ballot(lane_first || lane_last) != 0;
-    // p += dt * force(h); `par` selects the LDS slots of this step, which
-    // alternate with the step index (a wavefront one step ahead writes the
+    // p += dk * force(h); `par` selects the LDS slots of this kick, which
+    // alternate with the kick index (a wavefront one kick ahead writes the
     // other slot while its neighbours still read this one)
     auto kick = [&](auto par_c) {
         constexpr int par = decltype(par_c)::value;
@@ -247,32 +248,57 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             p[j] = acc;
         }
     };
-    // h += dt p, or the closing half step dt/2 p after the last kick
-    auto drift = [&](auto last_c) {
-        constexpr bool last = decltype(last_c)::value;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const R c = MASS ? (last ? R(0.5) * dtm[MASS ? j : 0] : dtm[MASS ? j : 0])
-                             : (last ? s_half : s_dt);
-            h[j] += c * p[j];
-        }
-    };
     using Even = std::integral_constant<int, 0>;
     using Odd = std::integral_constant<int, 1>;
-    int step = 0;
-    for (; step + 2 < n_steps; step += 2) {
+    auto integrate = [&](auto omelyan_c) {
+        constexpr bool OM = decltype(omelyan_c)::value;
+        constexpr double kLambda = 0.1931833275037836;
+        // drift factors: first, after an even kick, after an odd kick, last
+        constexpr double f_first = OM ? kLambda : 0.5;
+        constexpr double f_even = OM ? 1.0 - 2.0 * kLambda : 1.0;
+        constexpr double f_odd = OM ? 2.0 * kLambda : 1.0;
+        const R s_first = wave_uniform(static_cast<R>(f_first * dt));
+        const R s_even = wave_uniform(static_cast<R>(f_even * dt));
+        const R s_odd = wave_uniform(static_cast<R>(f_odd * dt));
+        // h += c p (identity mass: c = f dt; diagonal mass: c = f dt / m_t)
+        auto drift = [&](auto which_c) {
+            constexpr int which = decltype(which_c)::value;  // 0 first/last, 1 even, 2 odd
+            constexpr double f = which == 0 ? f_first : (which == 1 ? f_even : f_odd);
+            const R sc = which == 0 ? s_first : (which == 1 ? s_even : s_odd);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                R c;
+                if constexpr (MASS)
+                    c = f == 1.0 ? dtm[MASS ? j : 0] : static_cast<R>(f) * dtm[MASS ? j : 0];
+                else
+                    c = sc;
+                h[j] += c * p[j];
+            }
+        };
+        using First = std::integral_constant<int, 0>;
+        using AfterEven = std::integral_constant<int, 1>;
+        using AfterOdd = std::integral_constant<int, 2>;
+        const int n_kicks = OM ? 2 * n_steps : n_steps;
+        drift(First{});
+        int i = 0;
+        for (; i + 2 < n_kicks; i += 2) {
+            kick(Even{});
+            drift(AfterEven{});
+            kick(Odd{});
+            drift(AfterOdd{});
+        }
+        // one or two kicks remain; `i` is even
         kick(Even{});
-        drift(std::false_type{});
-        kick(Odd{});
-        drift(std::false_type{});
-    }
-    // one or two steps remain; `step` is even
-    kick(Even{});
-    if (n_steps - step == 2) {
-        drift(std::false_type{});
-        kick(Odd{});
-    }
-    drift(std::true_type{});
+        if (n_kicks - i == 2) {
+            drift(AfterEven{});
+            kick(Odd{});
+        }
+        drift(First{});  // the last drift has the first one's factor
+    };
+    if (A.omelyan)
+        integrate(std::true_type{});
+    else
+        integrate(std::false_type{});
 
     // ---- dH = sum over exact sites of per-site differences (FP64), and the
     //      sufficient statistics of the proposal and of the current state ----
