@@ -292,55 +292,70 @@ def run_batched(args):
     thetas = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
     jit = jitter_of(args, 0.5)
     level = level_of(args, True)
-    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
+    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN
     from paper_1603_08114_amd import autotune
-    dtau = 0.05 * (1000.0 / Ts) ** 0.25
-    kw = dict(chains_per_series=C_, precision=RSV_F32_MIXED, dtau_jitter=jit,
-              flags=RSV_FLAG_LEVEL_MOVE if level else 0)
-    S_t, NW_t, shape_table = autotune.best_shape(off, data["y"], data["log_rv"], h0, thetas,
-                                                 [(k, d) for d in dtau], n_sweeps=4, **kw)
-    print(f"[batched] autotuned tile shape S={S_t} NW={NW_t}: {shape_table}", file=sys.stderr,
-          flush=True)
-    smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, max_steps=k, seed=3,
-                         sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
-    sweep = 0
-    for _ in range(10):  # 10 windows of 50 warm-up sweeps
-        out = smp.sweep(sweep, 50, [(k, d) for d in dtau], update_theta=True,
-                        record=("delta_h",))
-        sweep += 50
-        dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
-        acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
-        dtau = dtau * np.exp(1.5 * (acc - 0.8))
-    lf = [(k, d) for d in dtau]
-    smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
-    sweep += 1
-    torch.cuda.synchronize()
-    n, bl = 2000, 40
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(smp.stream)
-    out = smp.sweep(sweep, n, lf, update_theta=True, record=("theta", "accepted"), batch_len=bl)
-    ev1.record(smp.stream)
-    torch.cuda.synchronize()
-    elapsed = ev0.elapsed_time(ev1) / 1e3
-    bsum = out["h_batch_sum"].cpu().numpy() / bl
-    sq = out["h_sq_sum"].cpu().numpy() / n
-    mean = bsum.mean(axis=0)
-    var = np.maximum(sq - mean * mean, 0.0)
-    ess_site = diagnostics.ess_batch_means(bsum, var, n)
-    th = out["theta"].cpu().numpy()  # (n, chains, 5)
-    per_series = np.empty(S_)
-    for s in range(S_):
-        e_h = 0.0
-        e_th = np.zeros(5)
-        T = int(Ts[s])
-        for j in range(C_):
-            c = s * C_ + j
-            start = C_ * int(off[s]) + j * T
-            e_h = e_h + ess_site[start:start + T]
-            e_th += diagnostics.ess_geyer(th[:, c, :])
-        per_series[s] = min(np.nanmin(e_h), np.nanmin(e_th))
-    rate = per_series / elapsed
+
+    def arm(omelyan):
+        """Warm-up, dtau adaptation and the measured sweeps of one integrator:
+        the leapfrog with k = 30, or Omelyan's scheme with k = 15 (the same 30
+        force evaluations per trajectory, twice the starting dtau)."""
+        k_ = k // 2 if omelyan else k
+        dtau = (2.0 if omelyan else 1.0) * 0.05 * (1000.0 / Ts) ** 0.25
+        kw = dict(chains_per_series=C_, precision=RSV_F32_MIXED, dtau_jitter=jit,
+                  flags=(RSV_FLAG_LEVEL_MOVE if level else 0)
+                  | (RSV_FLAG_OMELYAN if omelyan else 0))
+        S_t, NW_t, shape_table = autotune.best_shape(off, data["y"], data["log_rv"], h0, thetas,
+                                                     [(k_, d) for d in dtau], n_sweeps=4, **kw)
+        print(f"[batched] autotuned tile shape S={S_t} NW={NW_t}: {shape_table}", file=sys.stderr,
+              flush=True)
+        smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, max_steps=k_, seed=3,
+                             sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
+        sweep = 0
+        for _ in range(10):  # 10 windows of 50 warm-up sweeps
+            out = smp.sweep(sweep, 50, [(k_, d) for d in dtau], update_theta=True,
+                            record=("delta_h",))
+            sweep += 50
+            dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
+            acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
+            dtau = dtau * np.exp(1.5 * (acc - 0.8))
+        lf = [(k_, d) for d in dtau]
+        smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
+        sweep += 1
+        torch.cuda.synchronize()
+        n, bl = 2000, 40
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(smp.stream)
+        out = smp.sweep(sweep, n, lf, update_theta=True, record=("theta", "accepted"), batch_len=bl)
+        ev1.record(smp.stream)
+        torch.cuda.synchronize()
+        elapsed = ev0.elapsed_time(ev1) / 1e3
+        bsum = out["h_batch_sum"].cpu().numpy() / bl
+        sq = out["h_sq_sum"].cpu().numpy() / n
+        mean = bsum.mean(axis=0)
+        var = np.maximum(sq - mean * mean, 0.0)
+        ess_site = diagnostics.ess_batch_means(bsum, var, n)
+        th = out["theta"].cpu().numpy()  # (n, chains, 5)
+        per_series = np.empty(S_)
+        for s in range(S_):
+            e_h = 0.0
+            e_th = np.zeros(5)
+            T = int(Ts[s])
+            for j in range(C_):
+                c = s * C_ + j
+                start = C_ * int(off[s]) + j * T
+                e_h = e_h + ess_site[start:start + T]
+                e_th += diagnostics.ess_geyer(th[:, c, :])
+            per_series[s] = min(np.nanmin(e_h), np.nanmin(e_th))
+        acc_rate = float(out["accepted"].float().mean().item())
+        smp.close()
+        return dict(rate=per_series / elapsed, elapsed=elapsed, n=n, dtau=dtau, S=S_t, NW=NW_t,
+                    table=shape_table, acceptance=acc_rate)
+
+    lf_arm = arm(False)
+    om_arm = arm(True)
+    rate, elapsed, n, dtau = lf_arm["rate"], lf_arm["elapsed"], lf_arm["n"], lf_arm["dtau"]
+    S_t, NW_t, shape_table = lf_arm["S"], lf_arm["NW"], lf_arm["table"]
     total_su = float(Ts.sum()) * C_ * k * n
     res = {"metric": METRIC, "value": float(np.median(rate)), "unit": "min-ESS/s (median over series)",
            "n_gpus": 1, "steps": n, "warmup": 500, "ms_per_step": elapsed / n * 1e3,
@@ -355,8 +370,16 @@ def run_batched(args):
                       "sites_per_lane": S_t, "waves_per_tile": NW_t},
            "autotune_seconds_per_sweep": shape_table,
            "min_over_series": float(rate.min()), "site_updates_per_s": total_su / elapsed,
-           "acceptance": float(out["accepted"].float().mean().item()),
-           "dtau_range": [float(dtau.min()), float(dtau.max())]}
+           "acceptance": lf_arm["acceptance"],
+           "dtau_range": [float(dtau.min()), float(dtau.max())],
+           "omelyan": {"integrator": "Omelyan 2nd-order minimum-norm, k=15 (30 force "
+                                     "evaluations, as the leapfrog's k=30)",
+                       "median_min_ess_per_s": float(np.median(om_arm["rate"])),
+                       "min_over_series": float(om_arm["rate"].min()),
+                       "ms_per_step": om_arm["elapsed"] / om_arm["n"] * 1e3,
+                       "acceptance": om_arm["acceptance"],
+                       "dtau_range": [float(om_arm["dtau"].min()), float(om_arm["dtau"].max())],
+                       "sites_per_lane": om_arm["S"], "waves_per_tile": om_arm["NW"]}}
     if args.cpu_sweeps > 0:
         import time as _t
         import oracle
