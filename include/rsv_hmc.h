@@ -105,7 +105,8 @@ typedef struct {
     double eta_shape, eta_scale, u_shape, u_scale;
 } rsv_prior;
 
-/* Leapfrog knobs of Sec. 3: k steps of size dtau. */
+/* Integrator knobs of Sec. 3: k steps of size dtau (leapfrog steps, or
+ * Omelyan steps under RSV_FLAG_OMELYAN). */
 typedef struct { int32_t n_steps; int32_t reserved; double dtau; } rsv_leapfrog;
 
 typedef struct {
@@ -200,7 +201,8 @@ rsv_status rsv_hmc_init(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta
 rsv_status rsv_hmc_momenta(rsv_ctx *c, uint64_t sweep, double *p_out);
 
 /* One HMC trajectory for every chain (Sec. 3): momentum refresh, k leapfrog
- * steps of eqs. (6)-(8), dH = H(p',h') - H(p,h) as a compensated FP64 sum
+ * steps of eqs. (6)-(8) (or of Omelyan's scheme under RSV_FLAG_OMELYAN),
+ * dH = H(p',h') - H(p,h) as a compensated FP64 sum
  * of per-site differences, and the Metropolis test accept iff
  * ln u < -dH (a non-finite dH rejects).  On acceptance the chain's state
  * becomes h', else it stays.  theta is not changed.
