@@ -60,6 +60,8 @@ def _load():
                                 C.c_double]),
         "orc_omelyan": (None, [_I64, _D, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
                                C.c_double]),
+        "orc_forest_ruth": (None, [_I64, _D, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
+                                   C.c_double]),
         "orc_delta_h": (C.c_double, [_I64, _D, _D, _D, _D, _D, _D, _D, P(Theta), C.c_int]),
         "orc_momenta": (None, [_U64, _U64, _U64, _I64, _D, _D]),
         "orc_log_u": (C.c_double, [_U64, _U64, _U64]),
@@ -178,7 +180,9 @@ def leapfrog(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
 
 INT_LEAPFROG = 0
 INT_OMELYAN = 1
+INT_FOREST_RUTH = 2
 OMELYAN_LAMBDA = 0.1931833275037836
+FOREST_RUTH_THETA = 1.3512071919596578
 
 
 def omelyan(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
@@ -189,6 +193,17 @@ def omelyan(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
     lm = None if log_m is None else _arr(log_m, T)
     _lib.orc_omelyan(T, _ptr(h), _ptr(p), _ptr(lm), _ptr(_arr(y2, T)), _ptr(_arr(r, T)),
                      C.byref(theta_struct(theta)), terms, int(k), float(dtau))
+    return h, p
+
+
+def forest_ruth(h, p, y2, r, theta, k, dtau, terms=TERMS_RSV, log_m=None):
+    """k steps of Forest and Ruth's fourth-order scheme (h first); returns
+    new (h, p) (inputs untouched)."""
+    h = _arr(h).copy(); T = h.size
+    p = _arr(p, T).copy()
+    lm = None if log_m is None else _arr(log_m, T)
+    _lib.orc_forest_ruth(T, _ptr(h), _ptr(p), _ptr(lm), _ptr(_arr(y2, T)), _ptr(_arr(r, T)),
+                         C.byref(theta_struct(theta)), terms, int(k), float(dtau))
     return h, p
 
 

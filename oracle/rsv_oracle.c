@@ -235,12 +235,43 @@ void orc_omelyan(int64_t T, double *h, double *p, const double *log_m,
     free(g);
 }
 
+/* Forest and Ruth's fourth-order scheme (Physica D 43 (1990) 105), the
+ * h-first composition of three leapfrogs of sizes theta, 1 - 2 theta, theta
+ * with theta = 1 / (2 - 2^(1/3)): each of the k steps moves h by
+ * theta/2 dtau, p by theta dtau, h by (1 - theta)/2 dtau, p by
+ * (1 - 2 theta) dtau, h by (1 - theta)/2 dtau, p by theta dtau, h by
+ * theta/2 dtau.  Three force evaluations per step. */
+void orc_forest_ruth(int64_t T, double *h, double *p, const double *log_m,
+                     const double *y2, const double *r, const orc_theta *th, int terms,
+                     int32_t k, double dtau)
+{
+    const double theta = ORC_FOREST_RUTH_THETA;
+    const double drift[4] = { 0.5 * theta, 0.5 * (1.0 - theta), 0.5 * (1.0 - theta),
+                              0.5 * theta };
+    const double kick[3] = { theta, 1.0 - 2.0 * theta, theta };
+    double *g = (double *)malloc((size_t)T * sizeof(double));
+    double *inv_m = (double *)malloc((size_t)T * sizeof(double));
+    for (int64_t t = 0; t < T; ++t) inv_m[t] = log_m ? exp(-log_m[t]) : 1.0;
+    for (int32_t step = 0; step < k; ++step) {
+        for (int s = 0; s < 3; ++s) {
+            for (int64_t t = 0; t < T; ++t) h[t] = h[t] + drift[s] * dtau * p[t] * inv_m[t];
+            orc_grad(T, h, y2, r, th, terms, g);
+            for (int64_t t = 0; t < T; ++t) p[t] = p[t] - kick[s] * dtau * g[t];
+        }
+        for (int64_t t = 0; t < T; ++t) h[t] = h[t] + drift[3] * dtau * p[t] * inv_m[t];
+    }
+    free(inv_m);
+    free(g);
+}
+
 void orc_integrate(int64_t T, double *h, double *p, const double *log_m,
                    const double *y2, const double *r, const orc_theta *th, int terms,
                    int32_t k, double dtau, int integrator)
 {
     if (integrator == ORC_INT_OMELYAN)
         orc_omelyan(T, h, p, log_m, y2, r, th, terms, k, dtau);
+    else if (integrator == ORC_INT_FOREST_RUTH)
+        orc_forest_ruth(T, h, p, log_m, y2, r, th, terms, k, dtau);
     else
         orc_leapfrog(T, h, p, log_m, y2, r, th, terms, k, dtau);
 }

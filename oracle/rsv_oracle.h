@@ -75,14 +75,20 @@ double orc_hamiltonian(int64_t T, const double *h, const double *p, const double
 void orc_leapfrog(int64_t T, double *h, double *p, const double *log_m,
                   const double *y2, const double *r, const orc_theta *th, int terms,
                   int32_t k, double dtau);
-/* Integrators of the trajectory: the paper's leapfrog, or Omelyan's
- * second-order minimum-norm scheme (h-first form, lambda below). */
-enum { ORC_INT_LEAPFROG = 0, ORC_INT_OMELYAN = 1 };
+/* Integrators of the trajectory: the paper's leapfrog, Omelyan's
+ * second-order minimum-norm scheme (h-first form, lambda below), or Forest
+ * and Ruth's fourth-order scheme (h-first form, theta below). */
+enum { ORC_INT_LEAPFROG = 0, ORC_INT_OMELYAN = 1, ORC_INT_FOREST_RUTH = 2 };
 #define ORC_OMELYAN_LAMBDA 0.1931833275037836
+#define ORC_FOREST_RUTH_THETA 1.3512071919596578
 /* k steps of the Omelyan scheme, in place (2k force evaluations). */
 void orc_omelyan(int64_t T, double *h, double *p, const double *log_m,
                  const double *y2, const double *r, const orc_theta *th, int terms,
                  int32_t k, double dtau);
+/* k steps of the Forest-Ruth scheme, in place (3k force evaluations). */
+void orc_forest_ruth(int64_t T, double *h, double *p, const double *log_m,
+                     const double *y2, const double *r, const orc_theta *th, int terms,
+                     int32_t k, double dtau);
 /* k steps of the integrator `integrator` (ORC_INT_*), in place. */
 void orc_integrate(int64_t T, double *h, double *p, const double *log_m,
                    const double *y2, const double *r, const orc_theta *th, int terms,
