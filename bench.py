@@ -180,22 +180,27 @@ def min_ess_from_traces(h_trace, theta_trace):
     return float(min(np.nanmin(ess_h), np.nanmin(ess_th))), ess_h, ess_th
 
 
-def small_chain(jit, level, with_oracle, omelyan=False):
+def small_chain(jit, level, with_oracle, integrator="leapfrog"):
     """The single-series run (T = 1000, k = 20, dtau = 0.05, 500 burn-in +
     5000 sweeps, theta every sweep, FP64) on the GPU and, optionally, the same
-    chain on the oracle.  With omelyan, the trajectory is 10 Omelyan steps of
-    0.1: the same length and the same 20 force evaluations.  Returns (GPU
-    record, oracle record or None)."""
+    chain on the oracle.  The trajectory has length 1 in every case: 20
+    leapfrog steps of 0.05, 10 Omelyan steps of 0.1 (20 force evaluations) or
+    7 Forest-Ruth steps of 1/7 (21).  Returns (GPU record, oracle record or
+    None)."""
     import torch
     import synth
     from paper_1603_08114_amd import api
-    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN
+    from paper_1603_08114_amd._lib import (RSV_FLAG_FOREST_RUTH, RSV_FLAG_LEVEL_MOVE,
+                                           RSV_FLAG_OMELYAN)
     T, k, dtau, burn, n = 1000, 20, 0.05, 500, 5000
-    if omelyan:
-        k, dtau = 10, 0.1
+    iflag = 0
+    if integrator == "omelyan":
+        k, dtau, iflag = 10, 0.1, RSV_FLAG_OMELYAN
+    elif integrator == "forest_ruth":
+        k, dtau, iflag = 7, 1.0 / 7.0, RSV_FLAG_FOREST_RUTH
     theta = dict(synth.THETA_STAR)
     y, lr, h_true = synth.simulate_rsv(T, theta, 1)
-    flags = (RSV_FLAG_LEVEL_MOVE if level else 0) | (RSV_FLAG_OMELYAN if omelyan else 0)
+    flags = (RSV_FLAG_LEVEL_MOVE if level else 0) | iflag
     smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1, dtau_jitter=jit,
                          flags=flags)
     smp.sweep(0, burn, (k, dtau), update_theta=True, record=())
@@ -216,16 +221,17 @@ def small_chain(jit, level, with_oracle, omelyan=False):
                                      map(float, ess_th))),
            "acceptance": float(out["accepted"].float().mean().item()),
            "site_updates_per_s": T * k * n / elapsed, "k": k, "dtau": dtau,
-           "integrator": "omelyan" if omelyan else "leapfrog"}
+           "integrator": integrator}
     smp.close()
     ref = None
     if with_oracle:
         import time as _t
         import oracle
+        iorc = {"leapfrog": oracle.INT_LEAPFROG, "omelyan": oracle.INT_OMELYAN,
+                "forest_ruth": oracle.INT_FOREST_RUTH}[integrator]
         t0 = _t.perf_counter()
         r = oracle.run(h_true, theta, y * y, lr, k, dtau, burn + n, seed=1, keep_h=True,
-                       jitter=jit, moves=oracle.MOVE_LEVEL if level else 0,
-                       integrator=oracle.INT_OMELYAN if omelyan else oracle.INT_LEAPFROG)
+                       jitter=jit, moves=oracle.MOVE_LEVEL if level else 0, integrator=iorc)
         dt = _t.perf_counter() - t0
         m_ref, _, _ = min_ess_from_traces(r["h_trace"][burn:], r["theta_trace"][burn:])
         ref = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s", "cores": 1,
@@ -240,8 +246,9 @@ def run_small(args):
     """Single series, T = 1000, k = 20, dtau = 0.05, 500 burn-in + 5000 sweeps,
     theta every sweep, FP64: min over {h_t} and theta of the ESS per second.
     value: the paper's sampler (fixed dtau, Gibbs theta); beside it the same
-    workload with step-size jitter 0.5 and the level move, with the leapfrog and
-    with Omelyan's integrator at the same cost per trajectory."""
+    workload with step-size jitter 0.5 and the level move, with the leapfrog,
+    Omelyan's and Forest-Ruth's integrators at about the same cost per
+    trajectory."""
     jit = jitter_of(args, 0.0)
     level = level_of(args, False)
     gpu, ref = small_chain(jit, level, args.cpu_sweeps > 0)
@@ -261,8 +268,10 @@ def run_small(args):
     if not jit and not level:
         g2, r2 = small_chain(0.5, True, args.cpu_sweeps > 0)
         res["with_jitter_and_level_move"] = {"gpu": g2, "oracle": r2}
-        g3, r3 = small_chain(0.5, True, args.cpu_sweeps > 0, omelyan=True)
+        g3, r3 = small_chain(0.5, True, args.cpu_sweeps > 0, integrator="omelyan")
         res["omelyan_with_jitter_and_level_move"] = {"gpu": g3, "oracle": r3}
+        g4, r4 = small_chain(0.5, True, args.cpu_sweeps > 0, integrator="forest_ruth")
+        res["forest_ruth_with_jitter_and_level_move"] = {"gpu": g4, "oracle": r4}
     return res
 
 

@@ -91,8 +91,20 @@ enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
  *   Comput. Phys. Commun. 151 (2003) 272).  Two force evaluations per step,
  *   so a step costs about twice a leapfrog step and the halo of a tile is
  *   sized for 2 n_steps (max_steps is checked against that).  Off by
- *   default. */
-enum { RSV_FLAG_NO_RESIDENT = 1, RSV_FLAG_LEVEL_MOVE = 2, RSV_FLAG_OMELYAN = 4 };
+ *   default.
+ * RSV_FLAG_FOREST_RUTH: Forest and Ruth's fourth-order scheme (Physica D 43
+ *   (1990) 105) instead: each step moves h by theta/2 dtau, p by theta dtau,
+ *   h by (1 - theta)/2 dtau, p by (1 - 2 theta) dtau, h by (1 - theta)/2
+ *   dtau, p by theta dtau, h by theta/2 dtau, theta = 1/(2 - 2^(1/3)).
+ *   Three force evaluations per step; the halo is sized for 3 n_steps.  At
+ *   most one of RSV_FLAG_OMELYAN and RSV_FLAG_FOREST_RUTH (EINVAL if both).
+ *   Off by default. */
+enum {
+    RSV_FLAG_NO_RESIDENT = 1,
+    RSV_FLAG_LEVEL_MOVE = 2,
+    RSV_FLAG_OMELYAN = 4,
+    RSV_FLAG_FOREST_RUTH = 8
+};
 
 /* theta of Sec. 2. */
 typedef struct { double phi, mu, xi, sig2_eta, sig2_u; } rsv_theta;
@@ -106,7 +118,7 @@ typedef struct {
 } rsv_prior;
 
 /* Integrator knobs of Sec. 3: k steps of size dtau (leapfrog steps, or
- * Omelyan steps under RSV_FLAG_OMELYAN). */
+ * Omelyan / Forest-Ruth steps under their flags). */
 typedef struct { int32_t n_steps; int32_t reserved; double dtau; } rsv_leapfrog;
 
 typedef struct {
@@ -201,7 +213,7 @@ rsv_status rsv_hmc_init(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta
 rsv_status rsv_hmc_momenta(rsv_ctx *c, uint64_t sweep, double *p_out);
 
 /* One HMC trajectory for every chain (Sec. 3): momentum refresh, k leapfrog
- * steps of eqs. (6)-(8) (or of Omelyan's scheme under RSV_FLAG_OMELYAN),
+ * steps of eqs. (6)-(8) (or of the scheme an integrator flag selects),
  * dH = H(p',h') - H(p,h) as a compensated FP64 sum
  * of per-site differences, and the Metropolis test accept iff
  * ln u < -dH (a non-finite dH rejects).  On acceptance the chain's state

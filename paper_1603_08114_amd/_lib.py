@@ -17,6 +17,7 @@ RSV_TERM_RETURN, RSV_TERM_RV, RSV_TERMS_RSV = 1, 2, 3
 RSV_FLAG_NO_RESIDENT = 1
 RSV_FLAG_LEVEL_MOVE = 2
 RSV_FLAG_OMELYAN = 4
+RSV_FLAG_FOREST_RUTH = 8
 
 THETA_KEYS = ("phi", "mu", "xi", "sig2_eta", "sig2_u")
 PRIOR_KEYS = ("mu_mean", "mu_var", "xi_mean", "xi_var",

@@ -54,9 +54,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 // halo covers the kicks of a trajectory plus the bond to the next site.
 int halo_for(int n_kicks) { return (n_kicks + 1 + 3) & ~3; }
 
-// Kicks per trajectory of n_steps: one per leapfrog step, two per Omelyan step.
+// Kicks per trajectory of n_steps: one per leapfrog step, two per Omelyan
+// step, three per Forest-Ruth step.
 int kicks_for(int32_t flags, int n_steps) {
-    return (flags & RSV_FLAG_OMELYAN) ? 2 * n_steps : n_steps;
+    if (flags & RSV_FLAG_OMELYAN) return 2 * n_steps;
+    if (flags & RSV_FLAG_FOREST_RUTH) return 3 * n_steps;
+    return n_steps;
 }
 
 // Tile decomposition of one chain of length T for tiles of NW wavefronts
@@ -121,8 +124,11 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
     if (!(pb->dtau_jitter >= 0.0 && pb->dtau_jitter < 1.0))
         return fail(RSV_EINVAL, "dtau_jitter must be in [0, 1)");
-    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE | RSV_FLAG_OMELYAN))
+    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE | RSV_FLAG_OMELYAN |
+                      RSV_FLAG_FOREST_RUTH))
         return fail(RSV_EINVAL, "unknown flags 0x%x", pb->flags);
+    if ((pb->flags & RSV_FLAG_OMELYAN) && (pb->flags & RSV_FLAG_FOREST_RUTH))
+        return fail(RSV_EINVAL, "at most one integrator flag");
     const rsv_prior& p = pb->prior;
     if (!(p.mu_var > 0 && p.xi_var > 0 && p.eta_shape > 0 && p.eta_scale > 0 && p.u_shape > 0 &&
           p.u_scale > 0 && std::isfinite(p.mu_mean) && std::isfinite(p.xi_mean) &&
@@ -338,7 +344,9 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.acc_sum = nullptr;
     a.acc_sq = nullptr;
     a.terms = c->pb.terms;
-    a.omelyan = (c->pb.flags & RSV_FLAG_OMELYAN) ? 1 : 0;
+    a.integrator = (c->pb.flags & RSV_FLAG_OMELYAN)       ? kIntOmelyan
+                   : (c->pb.flags & RSV_FLAG_FOREST_RUTH) ? kIntForestRuth
+                                                          : kIntLeapfrog;
     return a;
 }
 

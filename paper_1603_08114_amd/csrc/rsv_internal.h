@@ -48,6 +48,9 @@ constexpr int kEdge = 4;
 enum { kCntNonfiniteDH = 0, kCntNonfiniteState = 1, kCntNonfiniteData = 2, kCntGammaExhausted = 3,
        kNumCounters = 8 };
 
+// Integrators of the trajectory kernel.
+enum : int32_t { kIntLeapfrog = 0, kIntOmelyan = 1, kIntForestRuth = 2 };
+
 template <typename R>
 struct TrajArgs {
     const TileDesc* tiles;
@@ -75,7 +78,7 @@ struct TrajArgs {
     float* acc_sum;             // per state entry: add the state the trajectory
     float* acc_sq;              // starts from, and its square (or nullptr)
     int32_t terms;
-    int32_t omelyan;            // 1: Omelyan's integrator (2 kicks per step)
+    int32_t integrator;         // kIntLeapfrog, kIntOmelyan or kIntForestRuth
 };
 
 struct FinalizeArgs {

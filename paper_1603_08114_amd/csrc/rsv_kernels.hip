@@ -97,8 +97,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const double inv_se = 1.0 / th.sig2_eta;
     const double inv_su = rv ? 1.0 / th.sig2_u : 0.0;
     const double dt = step_size(A.seed, A.sweep, static_cast<uint64_t>(td.chain), cd.dtau, A.jitter);
-    // momentum steps: dt (leapfrog) or dt/2 (Omelyan: two per step)
-    const double dk = A.omelyan ? 0.5 * dt : dt;
+    // momentum steps: dt (leapfrog), dt/2 (Omelyan: two per step), or dt
+    // times a per-kick factor (Forest-Ruth: three per step)
+    const double dk = A.integrator == kIntOmelyan ? 0.5 * dt : dt;
     // force g_t = c_t + alpha h_t - beta (h_{t-1} + h_{t+1}) - s_t e^{-h_t} / 2
     const double alpha = (1.0 + phi * phi) * inv_se + inv_su;
     const double beta = phi * inv_se;
@@ -198,13 +199,16 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
-    // ---- integrator: the leapfrog of eqs. (6)-(8), or Omelyan's scheme ----
+    // ---- integrator: the leapfrog of eqs. (6)-(8), Omelyan's or Forest-Ruth's ----
     // Both are a chain of momentum steps (kicks) p += dk * force(h), all
     // alike, with position steps (drifts) h += c dt p / m between them:
     //   leapfrog, k kicks:  c = 1/2, then 1 between kicks, 1/2 at the end
     //                       (adjacent half steps of consecutive steps merged);
     //   Omelyan, 2k kicks:  c = lambda, then 1 - 2 lambda and 2 lambda in
-    //                       turn, lambda at the end.
+    //                       turn, lambda at the end;
+    //   Forest-Ruth, 3k kicks of theta, 1 - 2 theta, theta (times dt):
+    //                       c = theta/2, then (1 - theta)/2, (1 - theta)/2,
+    //                       theta in turn, theta/2 at the end.
     // Per-tile constants live in scalar registers.
     const R s_mda = wave_uniform(mda), s_db = wave_uniform(db);
     const R s_mu = wave_uniform(mu_r), s_phi = wave_uniform(phi_r);
@@ -216,8 +220,11 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     // p += dk * force(h); `par` selects the LDS slots of this kick, which
     // alternate with the kick index (a wavefront one kick ahead writes the
     // other slot while its neighbours still read this one)
-    auto kick = [&](auto par_c) {
+    // With `scaled`, the constants are for a step of dt and the force is
+    // added times the kick's factor `kf` (the same five operations per site).
+    auto kick = [&](auto par_c, auto scaled_c, R kf) {
         constexpr int par = decltype(par_c)::value;
+        constexpr bool scaled = decltype(scaled_c)::value;
         R hl0 = from_lower(h[S - 1]);
         R hrS = from_upper(h[0]);
         if constexpr (NW > 1) {
@@ -241,13 +248,21 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             if constexpr (EDGE) {
                 if (j < S - 1 && t0 + j == T - 1) hr = ghost_neighbour(h[j], s_mu, s_phi);
             }
-            R acc = p[j] + dc[j];
-            acc += s_mda * h[j];
-            acc += s_db * (hl + hr);
-            if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
-            p[j] = acc;
+            if constexpr (scaled) {
+                R acc = dc[j] + s_mda * h[j];
+                acc += s_db * (hl + hr);
+                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
+                p[j] += kf * acc;
+            } else {
+                R acc = p[j] + dc[j];
+                acc += s_mda * h[j];
+                acc += s_db * (hl + hr);
+                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
+                p[j] = acc;
+            }
         }
     };
+    using Plain = std::false_type;
     using Even = std::integral_constant<int, 0>;
     using Odd = std::integral_constant<int, 1>;
     auto integrate = [&](auto omelyan_c) {
@@ -282,21 +297,62 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         drift(First{});
         int i = 0;
         for (; i + 2 < n_kicks; i += 2) {
-            kick(Even{});
+            kick(Even{}, Plain{}, R(0));
             drift(AfterEven{});
-            kick(Odd{});
+            kick(Odd{}, Plain{}, R(0));
             drift(AfterOdd{});
         }
         // one or two kicks remain; `i` is even
-        kick(Even{});
+        kick(Even{}, Plain{}, R(0));
         if (n_kicks - i == 2) {
             drift(AfterEven{});
-            kick(Odd{});
+            kick(Odd{}, Plain{}, R(0));
         }
         drift(First{});  // the last drift has the first one's factor
     };
-    if (A.omelyan)
+    // Forest-Ruth: factors change with the kick index modulo 3 (a scalar)
+    auto integrate_fr = [&]() {
+        constexpr double kTheta = 1.3512071919596578;
+        const R kf_outer = wave_uniform(static_cast<R>(kTheta));
+        const R kf_mid = wave_uniform(static_cast<R>(1.0 - 2.0 * kTheta));
+        const R f_half = wave_uniform(static_cast<R>(0.5 * kTheta));
+        const R f_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta)));
+        const R f_full = wave_uniform(static_cast<R>(kTheta));
+        const R c_half = wave_uniform(static_cast<R>(0.5 * kTheta * dt));
+        const R c_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta) * dt));
+        const R c_full = wave_uniform(static_cast<R>(kTheta * dt));
+        // h += c p: c = f dt (identity mass) or f dt / m_t
+        auto drift_by = [&](R f, R c) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const R cj = MASS ? f * dtm[MASS ? j : 0] : c;
+                h[j] += cj * p[j];
+            }
+        };
+        using Scaled = std::true_type;
+        const int n_kicks = 3 * n_steps;
+        drift_by(f_half, c_half);
+        int i = 0, m = 0;  // m = i mod 3
+        for (; i + 2 < n_kicks; i += 2) {
+            kick(Even{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+            kick(Odd{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+        }
+        kick(Even{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+        if (n_kicks - i == 2) {
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+            kick(Odd{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+        }
+        drift_by(f_half, c_half);  // the last kick is the third of a step
+    };
+    if (A.integrator == kIntOmelyan)
         integrate(std::true_type{});
+    else if (A.integrator == kIntForestRuth)
+        integrate_fr();
     else
         integrate(std::false_type{});
 

@@ -69,7 +69,10 @@ def test_workspace_and_state_sizes():
     dict(offsets=[0, 100], waves_per_tile=3),
     dict(offsets=[0, 100], dtau_jitter=1.0),
     dict(offsets=[0, 100], dtau_jitter=-0.1),
-    dict(offsets=[0, 100], flags=8),
+    dict(offsets=[0, 100], flags=16),                                  # unknown flag
+    dict(offsets=[0, 100], flags=4 | 8),                               # two integrators
+    dict(offsets=[0, 3000], max_steps=50, sites_per_lane=4, waves_per_tile=1,
+         flags=8),                                                    # 3k-kick halo > tile
     dict(offsets=[0, 100], prior=dict(mu_var=-1.0)),
 ])
 def test_invalid_problems_rejected_on_host(bad):

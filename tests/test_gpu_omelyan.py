@@ -1,10 +1,11 @@
-"""Omelyan integrator (RSV_FLAG_OMELYAN) on the GPU against the oracle.
+"""Omelyan (RSV_FLAG_OMELYAN) and Forest-Ruth (RSV_FLAG_FOREST_RUTH)
+integrators on the GPU against the oracle.
 
 Same bars as the leapfrog: FP64 h' rel <= 1e-12 and dH abs <= 1e-9 (relative
 above 1), identical accept decisions away from near-ties, theta traces
 rel <= 1e-10; FP32-mixed within the FP32 rounding bound of the leapfrog test
-(its error per kick is the same and there are twice as many kicks of half
-the size).  The halo of a tile covers 2k kicks, so the multi-tile cases
+(its error per kick is the same and there are two or three times as many
+kicks).  The halo of a tile covers 2k or 3k kicks, so the multi-tile cases
 check that the tiling follows the integrator."""
 import numpy as np
 import pytest
@@ -16,19 +17,29 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_1603_08114_amd import api  # noqa: E402
-from paper_1603_08114_amd._lib import (RSV_F32_MIXED, RSV_FLAG_LEVEL_MOVE,  # noqa: E402
-                                       RSV_FLAG_NO_RESIDENT, RSV_FLAG_OMELYAN)
+from paper_1603_08114_amd._lib import (RSV_F32_MIXED, RSV_FLAG_FOREST_RUTH,  # noqa: E402
+                                       RSV_FLAG_LEVEL_MOVE, RSV_FLAG_NO_RESIDENT,
+                                       RSV_FLAG_OMELYAN)
 from test_gpu_parity import (NEAR_TIE, TH, _compare_runs, chain_slices,  # noqa: E402
                              make_series, rel_inf, sampler, state_from)
 
 OM = oracle.INT_OMELYAN
+FR = oracle.INT_FOREST_RUTH
+# (flag, oracle integrator, oracle step function, steps per trajectory divisor)
+INTEGRATORS = {"omelyan": (RSV_FLAG_OMELYAN, OM, oracle.omelyan),
+               "forest_ruth": (RSV_FLAG_FOREST_RUTH, FR, oracle.forest_ruth)}
 
 
 @pytest.mark.parametrize("Ts,C,k,dt", [([1000], 1, 10, 0.1), ([3], 1, 10, 0.1),
                                        ([513, 4000], 2, 15, 0.08), ([9001], 1, 25, 0.04)])
 @pytest.mark.parametrize("S,NW", [(4, 1), (8, 1), (4, 4), (8, 2), (8, 8)])
-def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
-    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW, flags=RSV_FLAG_OMELYAN)
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW, name):
+    flag, _, step_fn = INTEGRATORS[name]
+    if name == "forest_ruth":
+        # about the same kicks; dtau well inside its stability bound (omega dtau < 1.57)
+        k, dt = (2 * k) // 3, dt * 0.8
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, S=S, NW=NW, flags=flag)
     rng = np.random.default_rng(3)
     p0 = rng.standard_normal(h0.size)
     log_u = np.log(rng.uniform(size=smp.n_chains))
@@ -37,7 +48,7 @@ def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
     dh, acc = dh.cpu().numpy(), acc.cpu().numpy()
     for c, (s, sl) in enumerate(chain_slices(offsets, C)):
         y2, r = ys[s] ** 2, rs[s]
-        h1, p1 = oracle.omelyan(h0[sl], p0[sl], y2, r, th[c], k, dt)
+        h1, p1 = step_fn(h0[sl], p0[sl], y2, r, th[c], k, dt)
         dH = oracle.delta_h(h0[sl], p0[sl], h1, p1, y2, r, th[c])
         assert abs(dh[c] - dH) <= 1e-9 * max(1.0, abs(dH)), (c, dh[c], dH)
         if abs(dH + log_u[c]) > NEAR_TIE:
@@ -47,28 +58,34 @@ def test_trajectory_injected_momenta_f64(Ts, C, k, dt, S, NW):
             assert rel_inf(h_gpu[sl], expect) <= 1e-12, (c, rel_inf(h_gpu[sl], expect))
 
 
-def test_trajectory_own_streams_with_mass_multi_tile_f64():
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_trajectory_own_streams_with_mass_multi_tile_f64(name):
+    flag, integ, _ = INTEGRATORS[name]
     Ts, C, k, dt = [5000, 1300], 2, 15, 0.16
+    if name == "forest_ruth":  # light sites (m ~ 1.3) need omega dtau < 1.57
+        k, dt = 10, 0.1
     lm = np.clip(2.4 + 0.7 * np.random.default_rng(4).standard_normal(sum(Ts)), -5, 5)
     lm = lm.astype(np.float32)
-    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, log_mass=lm, flags=RSV_FLAG_OMELYAN)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, log_mass=lm, flags=flag)
     dh, acc = smp.trajectory(6, (k, dt))
     h_gpu, dh, acc = smp.h.cpu().numpy(), dh.cpu().numpy(), acc.cpu().numpy()
     lmd = lm.astype(np.float64)
     for c, (s, sl) in enumerate(chain_slices(offsets, C)):
         dsl = slice(int(offsets[s]), int(offsets[s + 1]))
         ref = oracle.trajectory(h0[sl], ys[s] ** 2, rs[s], th[c], k, dt, seed=smp.pb.seed,
-                                sweep=6, chain=c, log_m=lmd[dsl], integrator=OM)
+                                sweep=6, chain=c, log_m=lmd[dsl], integrator=integ)
         assert abs(dh[c] - ref["dH"]) <= 1e-9 * max(1.0, abs(ref["dH"]))
         if abs(ref["dH"] + oracle.log_u(smp.pb.seed, 6, c)) > NEAR_TIE:
             assert bool(acc[c]) == ref["accepted"]
             assert rel_inf(h_gpu[sl], ref["h"]) <= 1e-12
 
 
-def test_f32_mixed_trajectory_error_vs_f64():
-    k, dt = 10, 0.1
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_f32_mixed_trajectory_error_vs_f64(name):
+    flag, _, step_fn = INTEGRATORS[name]
+    k, dt = (10, 0.1) if name == "omelyan" else (7, 0.08)
     smp, offsets, ys, rs, h0, th = sampler([1000, 2500], 1, k=k, precision=RSV_F32_MIXED,
-                                           flags=RSV_FLAG_OMELYAN)
+                                           flags=flag)
     rng = np.random.default_rng(8)
     p0 = rng.standard_normal(smp.n_state)
     dh, acc = smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
@@ -76,7 +93,7 @@ def test_f32_mixed_trajectory_error_vs_f64():
     h0_32 = h0.astype(np.float32).astype(np.float64)
     for c, (s, sl) in enumerate(chain_slices(offsets, 1)):
         p32 = p0[sl].astype(np.float32).astype(np.float64)
-        h1, p1 = oracle.omelyan(h0_32[sl], p32, ys[s] ** 2, rs[s], TH, k, dt)
+        h1, p1 = step_fn(h0_32[sl], p32, ys[s] ** 2, rs[s], TH, k, dt)
         dH = oracle.delta_h(h0_32[sl], p32, h1, p1, ys[s] ** 2, rs[s], TH)
         assert np.max(np.abs(h32[sl] - h1)) <= 2e-5
         assert abs(dh[c].item() - dH) <= 2e-3 * np.sqrt(sl.stop - sl.start) / 30
@@ -84,11 +101,15 @@ def test_f32_mixed_trajectory_error_vs_f64():
 
 
 @pytest.mark.parametrize("flags,j", [(0, 0.0), (RSV_FLAG_LEVEL_MOVE, 0.3)])
-def test_sweeps_match_oracle(flags, j):
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_sweeps_match_oracle(flags, j, name):
+    flag, integ, _ = INTEGRATORS[name]
     Ts, C, k, dt, n = [700, 2600], 2, 10, 0.08, 40
+    if name == "forest_ruth":
+        k, dt = 7, 0.05
     thetas = synth.draw_batch_thetas(len(Ts), 8)
     smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, thetas=thetas, dtau_jitter=j,
-                                           flags=flags | RSV_FLAG_OMELYAN)
+                                           flags=flags | flag)
     out = smp.sweep(30, n, (k, dt), update_theta=True)
     acc = out["accepted"].cpu().numpy()
     dh = out["delta_h"].cpu().numpy()
@@ -97,7 +118,7 @@ def test_sweeps_match_oracle(flags, j):
     moves = oracle.MOVE_LEVEL if flags & RSV_FLAG_LEVEL_MOVE else 0
     for c, (s, sl) in enumerate(chain_slices(offsets, C)):
         ref = oracle.run(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, seed=smp.pb.seed,
-                         chain=c, first_sweep=30, jitter=j, moves=moves, integrator=OM)
+                         chain=c, first_sweep=30, jitter=j, moves=moves, integrator=integ)
         m = _compare_runs(acc[:, c], dh[:, c], tht[:, c], ref, smp.pb.seed, c, 30)
         if m == n:
             assert rel_inf(h_end[sl], ref["h"]) <= 1e-10
@@ -105,8 +126,12 @@ def test_sweeps_match_oracle(flags, j):
 
 
 @pytest.mark.parametrize("precision", [0, RSV_F32_MIXED])
-def test_resident_sweeps_equal_per_kernel_sweeps(precision):
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_resident_sweeps_equal_per_kernel_sweeps(precision, name):
+    flag = INTEGRATORS[name][0]
     Ts, C, k, dt, n = [1000, 37, 2048, 1501], 3, 10, 0.08, 30
+    if name == "forest_ruth":  # stiff batch thetas (omega up to ~20) need a small dtau
+        k, dt = 7, 0.05
     thetas = synth.draw_batch_thetas(len(Ts), 9)
     offsets, ys, rs, hs = make_series(Ts, 300, thetas)
     h0 = state_from(hs, C, 0.02)
@@ -115,13 +140,17 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision):
     for path in (0, RSV_FLAG_NO_RESIDENT):
         smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                              chains_per_series=C, precision=precision, max_steps=k, seed=4,
-                             flags=RSV_FLAG_OMELYAN | RSV_FLAG_LEVEL_MOVE | path,
+                             flags=flag | RSV_FLAG_LEVEL_MOVE | path,
                              dtau_jitter=0.3, sites_per_lane=8, waves_per_tile=4)
         o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True)
         o["state"] = smp.h.clone()
         outs.append(o)
     for key in ("delta_h", "accepted", "theta", "h", "state"):
-        assert torch.equal(outs[0][key], outs[1][key]), key
+        a, b = outs[0][key], outs[1][key]
+        if a.is_floating_point():  # a diverged trajectory gives NaN on both paths
+            assert torch.equal(a.isnan(), b.isnan()), key
+            a, b = a.nan_to_num(nan=0.0), b.nan_to_num(nan=0.0)
+        assert torch.equal(a, b), key
     assert outs[0]["accepted"].float().mean() > 0.3
 
 
@@ -133,3 +162,5 @@ def test_halo_limit_follows_the_integrator():
     smp.close()
     with pytest.raises(api.RSVError):
         sampler([3000], 1, k=k, S=4, NW=1, flags=RSV_FLAG_OMELYAN)
+    with pytest.raises(api.RSVError):
+        sampler([3000], 1, k=70, S=4, NW=1, flags=RSV_FLAG_FOREST_RUTH)  # 2 x 212 > 256
