@@ -776,8 +776,27 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
     Comp acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
-    for (int i = tid; i < cd.tile_count; i += NT) {
-        const double* pp = A.partials + static_cast<int64_t>(cd.tile_begin + i) * kPart;
+    const double* chain_parts = A.partials + static_cast<int64_t>(cd.tile_begin) * kPart;
+    int i = tid;
+    if constexpr (NT >= 256) {
+        // chains of thousands of tiles: the partials of four tiles are loaded
+        // before any is added, so their memory latencies overlap (same order
+        // of additions as one tile at a time)
+        for (; i + 3 * NT < cd.tile_count; i += 4 * NT) {
+            double v[4][NQ];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    v[u][q] = chain_parts[static_cast<int64_t>(i + u * NT) * kPart + q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) comp_add(acc[q], v[u][q]);
+        }
+    }
+    for (; i < cd.tile_count; i += NT) {
+        const double* pp = chain_parts + static_cast<int64_t>(i) * kPart;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
     }
