@@ -100,6 +100,34 @@ def test_f32_mixed_trajectory_error_vs_f64(name):
     assert bool(acc.all())
 
 
+@pytest.mark.parametrize("name", list(INTEGRATORS))
+def test_f32_mixed_trajectory_with_mass_error_vs_f64(name):
+    """FP32 kicks and drifts with a diagonal mass against the FP64 oracle on
+    the same (FP32-rounded) momenta and mass; bounds as for the leapfrog."""
+    flag, _, step_fn = INTEGRATORS[name]
+    Ts, C = [3000, 700], 2
+    k, dt = (15, 0.16) if name == "omelyan" else (10, 0.1)
+    lm = np.clip(2.4 + 0.7 * np.random.default_rng(5).standard_normal(sum(Ts)), -5, 5)
+    lm = lm.astype(np.float32)
+    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, precision=RSV_F32_MIXED, log_mass=lm,
+                                           flags=flag)
+    rng = np.random.default_rng(8)
+    p0 = rng.standard_normal(smp.n_state) * np.exp(0.5 * np.concatenate(
+        [np.tile(lm[offsets[s]:offsets[s + 1]], C) for s in range(len(Ts))]))
+    dh, acc = smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
+    h32 = smp.h.cpu().numpy().astype(np.float64)
+    h0_32 = h0.astype(np.float32).astype(np.float64)
+    lmd = lm.astype(np.float64)
+    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
+        dsl = slice(int(offsets[s]), int(offsets[s + 1]))
+        p0c = p0[sl].astype(np.float32).astype(np.float64)
+        h1, p1 = step_fn(h0_32[sl], p0c, ys[s] ** 2, rs[s], th[c], k, dt, log_m=lmd[dsl])
+        dH = oracle.delta_h(h0_32[sl], p0c, h1, p1, ys[s] ** 2, rs[s], th[c], log_m=lmd[dsl])
+        assert np.max(np.abs(h32[sl] - h1)) <= 2e-5
+        assert abs(dh[c].item() - dH) <= 2e-3 * np.sqrt(sl.stop - sl.start) / 30
+    assert bool(acc.all())
+
+
 @pytest.mark.parametrize("flags,j", [(0, 0.0), (RSV_FLAG_LEVEL_MOVE, 0.3)])
 @pytest.mark.parametrize("name", list(INTEGRATORS))
 def test_sweeps_match_oracle(flags, j, name):
