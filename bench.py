@@ -101,7 +101,8 @@ def isa_figures(precision, S, NW):
     return table.get(f"{precision}_S{S}_W{NW}")
 
 
-KERNEL_SOURCES = ("rsv_kernels.hip", "rsv_device.h", "rsv_exp.h", "rsv_internal.h")
+KERNEL_SOURCES = ("rsv_traj.h", "rsv_traj_f64.hip", "rsv_traj_f32.hip", "rsv_device.h",
+                  "rsv_exp.h", "rsv_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_traj_traffic.json")
 
 

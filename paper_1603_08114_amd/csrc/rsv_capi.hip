@@ -2,8 +2,8 @@
 //
 // Owns no device memory: carves the caller's workspace, builds the tile
 // decomposition of every chain on the host (re-built only when the leapfrog
-// knobs change), and enqueues the kernels of rsv_kernels.hip on the caller's
-// stream.
+// knobs change), and enqueues the kernels (rsv_kernels.hip, rsv_traj_*.hip,
+// rsv_resident.hip) on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -123,13 +123,18 @@ struct ResidentArgs {
     double* sq_sum;
 };
 
-// Launchers (rsv_kernels.hip).  Each returns the hipError_t of its launch.
+// Launchers (rsv_kernels.hip, rsv_traj_*.hip, rsv_resident.hip).  Each returns the hipError_t of its launch.
 hipError_t launch_prepare(hipStream_t st, const double* y, const double* lrv, int64_t n,
                           double* y2_d, float* y2_f, float* lrv_f);
 hipError_t launch_validate(hipStream_t st, const double* y, const double* lrv, int64_t n_data,
                            const void* h, int64_t n_state, int precision, uint32_t* counters);
 hipError_t launch_traj(hipStream_t st, int precision, int S, int NW, bool mass,
                        const void* args);
+// Per-precision, per-mass instantiations (rsv_traj_{f64,f32}[_mass].hip).
+hipError_t launch_traj_f64(hipStream_t st, int S, int NW, const TrajArgs<double>& a);
+hipError_t launch_traj_f64_mass(hipStream_t st, int S, int NW, const TrajArgs<double>& a);
+hipError_t launch_traj_f32(hipStream_t st, int S, int NW, const TrajArgs<float>& a);
+hipError_t launch_traj_f32_mass(hipStream_t st, int S, int NW, const TrajArgs<float>& a);
 bool traj_shape_available(int precision, int S, int NW);
 void traj_default_shape(int precision, int* S, int* NW);
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain);

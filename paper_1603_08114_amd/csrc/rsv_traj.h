@@ -1,0 +1,958 @@
+// rsv_traj.h -- device code of the trajectory, finalize and resident
+// kernels, shared by the translation units that instantiate them (one per
+// precision and mass variant, so that they compile in parallel).
+//
+// Paper: T. Takaishi, arXiv:1603.08114.  The leapfrog of Sec. 3, eqs. (6)-(8)
+// (mapped to per-site GPU kernels in Sec. 5, eqs. (9)-(11)) is fused here into
+// one trajectory kernel that is blocked in time: each wavefront owns a tile
+// of one chain, holds h, p and the per-site constants of its tile in
+// registers (S contiguous sites per lane), exchanges the two boundary sites
+// of each lane with its neighbours by DPP lane shifts, and runs all k steps
+// without touching HBM.  Sites within k+1 of a tile's cut are recomputed by
+// the neighbouring tile (halo), so every exact site is produced once.
+#pragma once
+
+#include <type_traits>
+
+#include "rsv_device.h"
+#include "rsv_exp.h"
+#include "rsv_internal.h"
+
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wunused-function"
+
+namespace rsv {
+
+namespace {
+template <typename R>
+__device__ inline R ghost_neighbour(R h, R mu, R phi) {
+    // Substituting a_{-1} = phi a_0 (and a_{T} = phi a_{T-1}) into the interior
+    // AR(1) force reproduces the end-point forces of the stationary model.
+    return mu + phi * (h - mu);
+}
+
+template <typename R>
+__device__ inline R exp_neg(R x);
+template <>
+__device__ inline double exp_neg<double>(double x) { return exp_force(-x); }
+template <>
+__device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
+
+// Value of the current state at a site: the stored entry plus the chain's
+// pending level shift (0 unless level moves are on), rounded to the state's
+// precision.  Every reader of the current state goes through this.
+template <typename R>
+__device__ __forceinline__ R state_at(const R* hc, int64_t t, double shift) {
+    return static_cast<R>(static_cast<double>(hc[t]) + shift);
+}
+
+// Step size of one trajectory: dtau scaled by 1 + j (2u - 1), u the first
+// uniform of block 0 of the step stream (every tile of a chain draws the same
+// u).  Rounded step by step, without contraction, so the value is exact to
+// the last bit for any caller that evaluates the same three operations.
+__device__ inline double step_size(uint64_t seed, uint64_t sweep, uint64_t chain, double dtau,
+                                   double jitter) {
+#pragma clang fp contract(off)
+    if (!(jitter > 0.0)) return dtau;
+    double u[4];
+    uniforms4(seed, 0, sweep, chain, kTagStep, u);
+    const double w = 2.0 * u[0] - 1.0;
+    const double f = 1.0 + jitter * w;
+    return dtau * f;
+}
+
+// ---------------------------------------------------------------------------
+// Trajectory kernel: momentum refresh, k leapfrog steps, per-site dH terms and
+// sufficient statistics of h' and h, for one tile per group of NW wavefronts.
+// Lane g = 64*wave + lane of a tile holds sites [la + g*S, la + (g+1)*S).
+// Within a wavefront the end sites of each lane move by DPP lane shifts;
+// between the NW wavefronts of a tile they pass through LDS (one barrier per
+// leapfrog step, slots double-buffered by step parity).
+// ---------------------------------------------------------------------------
+template <typename R, int NW>
+struct TileShared {
+    R left[2][NW];   // h of the first site of each wavefront
+    R right[2][NW];  // h of the last site of each wavefront
+    double red[NW][kNQ];
+    double up1[NW], up0[NW];
+};
+
+// FP64 tiles keep the starting h, y^2 and ln RV of their sites in LDS for
+// the dH pass after the leapfrog loop (laid out [quantity][site j][lane],
+// each lane reading back only what it wrote), so that pass does not re-read
+// them from memory: the tiles in flight on one XCD hold more than its L2.
+// Enabled while a block's copy fits 48 KB (S * NW * tiles per block <= 32).
+template <typename R, int S, int NW, int TPB>
+struct Stage {
+    static constexpr bool on = sizeof(R) == sizeof(double) && S * NW * TPB <= 32;
+    static constexpr int n = on ? 3 * S * 64 * NW : 1;
+};
+
+template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET, bool STAGE>
+__device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW>& sh,
+                                          const int tile_id, const int wv, const int lane,
+                                          double* stage) {
+    const TileDesc td = A.tiles[tile_id];
+    const ChainDesc cd = A.chains[td.chain];
+    const rsv_theta th = A.theta[td.chain];
+
+    const int T = cd.T;
+    const int t0 = td.la + (wv * kWave + lane) * S;
+    const bool rv = (A.terms & RSV_TERM_RV) != 0;
+    const double phi = th.phi, mu = th.mu, xi = th.xi;
+    const double inv_se = 1.0 / th.sig2_eta;
+    const double inv_su = rv ? 1.0 / th.sig2_u : 0.0;
+    const double dt = step_size(A.seed, A.sweep, static_cast<uint64_t>(td.chain), cd.dtau, A.jitter);
+    // momentum steps: dt (leapfrog), dt/2 (Omelyan: two per step), or dt
+    // times a per-kick factor (Forest-Ruth: three per step)
+    const double dk = A.integrator == kIntOmelyan ? 0.5 * dt : dt;
+    // force g_t = c_t + alpha h_t - beta (h_{t-1} + h_{t+1}) - s_t e^{-h_t} / 2
+    const double alpha = (1.0 + phi * phi) * inv_se + inv_su;
+    const double beta = phi * inv_se;
+    const double c_base = (RET ? 0.5 : 0.0) + xi * inv_su - mu * (1.0 - phi) * (1.0 - phi) * inv_se;
+    const R mda = static_cast<R>(-dk * alpha);
+    const R db = static_cast<R>(dk * beta);
+    const R mu_r = static_cast<R>(mu), phi_r = static_cast<R>(phi);
+
+    R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1];
+    double kin0 = 0.0;  // kinetic energy of the exact sites at the start
+
+    const bool in_b = A.state_sel[td.chain] != 0;
+    const R* hc = (in_b ? A.h_b : A.h_a) + cd.h_off;
+    const double shift = A.shift ? A.shift[td.chain] : 0.0;
+    R* hp = (in_b ? const_cast<R*>(A.h_a) : A.h_b) + cd.h_off;
+    const R* y2 = A.y2 + cd.d_off;
+    const R* lr = A.lrv + cd.d_off;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int t = t0 + j;
+        const bool live = t < T;
+        h[j] = live ? state_at(hc, t, shift) : R(0);
+        const double yy = live ? static_cast<double>(y2[t]) : 0.0;
+        const double rr = live ? static_cast<double>(lr[t]) : 0.0;
+        dc[j] = static_cast<R>(-dk * (c_base - rr * inv_su));
+        ds[j] = RET ? static_cast<R>(0.5 * dk * yy) : R(0);
+        if constexpr (STAGE) {
+            constexpr int NT = 64 * NW;
+            const int g = wv * kWave + lane;
+            stage[(0 * S + j) * NT + g] = static_cast<double>(h[j]);
+            stage[(1 * S + j) * NT + g] = yy;
+            stage[(2 * S + j) * NT + g] = rr;
+        }
+    }
+    // batch-means accumulators of the starting state (the previous sweep's
+    // result) on the exact sites: the read-modify-writes overlap with the
+    // momentum draw instead of costing a separate pass over the state
+    if (A.acc_sum || A.acc_sq) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            if (t >= td.a && t < td.b) {
+                const float v = static_cast<float>(h[j]);
+                const int64_t i = cd.h_off + t;
+                if (A.acc_sum) A.acc_sum[i] += v;
+                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, A.acc_sq[i]);
+            }
+        }
+    }
+
+    // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
+    const double* minv = MASS ? A.mass_inv + cd.d_off : nullptr;
+    const double* msq = MASS ? A.mass_sqrt + cd.d_off : nullptr;
+    if (A.p0) {
+        const double* p0 = A.p0 + cd.h_off;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            p[j] = (t < T) ? static_cast<R>(p0[t]) : R(0);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < S / 4; ++g) {
+            double u[4], z[4];
+            uniforms4(A.seed, static_cast<uint64_t>((t0 >> 2) + g), A.sweep,
+                      static_cast<uint64_t>(td.chain), kTagMomentum, u);
+            gauss_pair(u[0], u[1], z[0], z[1]);
+            gauss_pair(u[2], u[3], z[2], z[3]);
+            // the mass table is read only after this block's normals exist:
+            // loads hoisted above the generator would hold registers through it
+            if constexpr (MASS) asm volatile("" ::: "memory");
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = 4 * g + q;
+                const int t = t0 + j;
+                double pm = z[q];
+                if constexpr (MASS) pm *= (t < T) ? msq[t] : 1.0;
+                p[j] = (t < T) ? static_cast<R>(pm) : R(0);
+            }
+        }
+    }
+    if constexpr (MASS) {
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            dtm[j] = static_cast<R>(dt * ((t < T) ? minv[t] : 1.0));
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int t = t0 + j;
+        if (t >= td.a && t < td.b) {
+            const double pj = static_cast<double>(p[j]);
+            const double im = MASS ? minv[t] : 1.0;
+            kin0 += 0.5 * pj * pj * im;
+        }
+    }
+
+    // ---- integrator: the leapfrog of eqs. (6)-(8), Omelyan's or Forest-Ruth's ----
+    // Both are a chain of momentum steps (kicks) p += dk * force(h), all
+    // alike, with position steps (drifts) h += c dt p / m between them:
+    //   leapfrog, k kicks:  c = 1/2, then 1 between kicks, 1/2 at the end
+    //                       (adjacent half steps of consecutive steps merged);
+    //   Omelyan, 2k kicks:  c = lambda, then 1 - 2 lambda and 2 lambda in
+    //                       turn, lambda at the end;
+    //   Forest-Ruth, 3k kicks of theta, 1 - 2 theta, theta (times dt):
+    //                       c = theta/2, then (1 - theta)/2, (1 - theta)/2,
+    //                       theta in turn, theta/2 at the end.
+    // Per-tile constants live in scalar registers.
+    const R s_mda = wave_uniform(mda), s_db = wave_uniform(db);
+    const R s_mu = wave_uniform(mu_r), s_phi = wave_uniform(phi_r);
+    const int n_steps = wave_uniform(cd.n_steps);
+    const bool lane_first = (t0 == 0);
+    const bool lane_last = (t0 + S == T);
+    // only the wavefronts that hold a chain end substitute a neighbour
+    const bool wave_end = __ballot(lane_first || lane_last) != 0;
+    // p += dk * force(h); `par` selects the LDS slots of this kick, which
+    // alternate with the kick index (a wavefront one kick ahead writes the
+    // other slot while its neighbours still read this one)
+    // With `scaled`, the constants are for a step of dt and the force is
+    // added times the kick's factor `kf` (the same five operations per site).
+    auto kick = [&](auto par_c, auto scaled_c, R kf) {
+        constexpr int par = decltype(par_c)::value;
+        constexpr bool scaled = decltype(scaled_c)::value;
+        R hl0 = from_lower(h[S - 1]);
+        R hrS = from_upper(h[0]);
+        if constexpr (NW > 1) {
+            if (lane == 0) sh.left[par][wv] = h[0];
+            if (lane == kWave - 1) sh.right[par][wv] = h[S - 1];
+            __syncthreads();
+            if (lane == 0 && wv > 0) hl0 = sh.right[par][wv - 1];
+            if (lane == kWave - 1 && wv < NW - 1) hrS = sh.left[par][wv + 1];
+        }
+        if (wave_end) {
+            // a real branch: without the barrier the compiler computes the
+            // substitutes in every wavefront and selects
+            asm volatile("" ::: "memory");
+            if (lane_first) hl0 = ghost_neighbour(h[0], s_mu, s_phi);
+            if (lane_last) hrS = ghost_neighbour(h[S - 1], s_mu, s_phi);
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const R hl = (j == 0) ? hl0 : h[j - 1];
+            R hr = (j == S - 1) ? hrS : h[j + 1];
+            if constexpr (EDGE) {
+                if (j < S - 1 && t0 + j == T - 1) hr = ghost_neighbour(h[j], s_mu, s_phi);
+            }
+            if constexpr (scaled) {
+                R acc = dc[j] + s_mda * h[j];
+                acc += s_db * (hl + hr);
+                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
+                p[j] += kf * acc;
+            } else {
+                R acc = p[j] + dc[j];
+                acc += s_mda * h[j];
+                acc += s_db * (hl + hr);
+                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
+                p[j] = acc;
+            }
+        }
+    };
+    using Plain = std::false_type;
+    using Even = std::integral_constant<int, 0>;
+    using Odd = std::integral_constant<int, 1>;
+    auto integrate = [&](auto omelyan_c) {
+        constexpr bool OM = decltype(omelyan_c)::value;
+        constexpr double kLambda = 0.1931833275037836;
+        // drift factors: first, after an even kick, after an odd kick, last
+        constexpr double f_first = OM ? kLambda : 0.5;
+        constexpr double f_even = OM ? 1.0 - 2.0 * kLambda : 1.0;
+        constexpr double f_odd = OM ? 2.0 * kLambda : 1.0;
+        const R s_first = wave_uniform(static_cast<R>(f_first * dt));
+        const R s_even = wave_uniform(static_cast<R>(f_even * dt));
+        const R s_odd = wave_uniform(static_cast<R>(f_odd * dt));
+        // h += c p (identity mass: c = f dt; diagonal mass: c = f dt / m_t)
+        auto drift = [&](auto which_c) {
+            constexpr int which = decltype(which_c)::value;  // 0 first/last, 1 even, 2 odd
+            constexpr double f = which == 0 ? f_first : (which == 1 ? f_even : f_odd);
+            const R sc = which == 0 ? s_first : (which == 1 ? s_even : s_odd);
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                R c;
+                if constexpr (MASS)
+                    c = f == 1.0 ? dtm[MASS ? j : 0] : static_cast<R>(f) * dtm[MASS ? j : 0];
+                else
+                    c = sc;
+                h[j] += c * p[j];
+            }
+        };
+        using First = std::integral_constant<int, 0>;
+        using AfterEven = std::integral_constant<int, 1>;
+        using AfterOdd = std::integral_constant<int, 2>;
+        const int n_kicks = OM ? 2 * n_steps : n_steps;
+        drift(First{});
+        int i = 0;
+        for (; i + 2 < n_kicks; i += 2) {
+            kick(Even{}, Plain{}, R(0));
+            drift(AfterEven{});
+            kick(Odd{}, Plain{}, R(0));
+            drift(AfterOdd{});
+        }
+        // one or two kicks remain; `i` is even
+        kick(Even{}, Plain{}, R(0));
+        if (n_kicks - i == 2) {
+            drift(AfterEven{});
+            kick(Odd{}, Plain{}, R(0));
+        }
+        drift(First{});  // the last drift has the first one's factor
+    };
+    // Forest-Ruth: factors change with the kick index modulo 3 (a scalar)
+    auto integrate_fr = [&]() {
+        constexpr double kTheta = 1.3512071919596578;
+        const R kf_outer = wave_uniform(static_cast<R>(kTheta));
+        const R kf_mid = wave_uniform(static_cast<R>(1.0 - 2.0 * kTheta));
+        const R f_half = wave_uniform(static_cast<R>(0.5 * kTheta));
+        const R f_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta)));
+        const R f_full = wave_uniform(static_cast<R>(kTheta));
+        const R c_half = wave_uniform(static_cast<R>(0.5 * kTheta * dt));
+        const R c_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta) * dt));
+        const R c_full = wave_uniform(static_cast<R>(kTheta * dt));
+        // h += c p: c = f dt (identity mass) or f dt / m_t
+        auto drift_by = [&](R f, R c) {
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const R cj = MASS ? f * dtm[MASS ? j : 0] : c;
+                h[j] += cj * p[j];
+            }
+        };
+        using Scaled = std::true_type;
+        const int n_kicks = 3 * n_steps;
+        drift_by(f_half, c_half);
+        int i = 0, m = 0;  // m = i mod 3
+        for (; i + 2 < n_kicks; i += 2) {
+            kick(Even{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+            kick(Odd{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+        }
+        kick(Even{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+        if (n_kicks - i == 2) {
+            drift_by(m == 2 ? f_full : f_mid, m == 2 ? c_full : c_mid);
+            m = m == 2 ? 0 : m + 1;
+            kick(Odd{}, Scaled{}, m == 1 ? kf_mid : kf_outer);
+        }
+        drift_by(f_half, c_half);  // the last kick is the third of a step
+    };
+    if (A.integrator == kIntOmelyan)
+        integrate(std::true_type{});
+    else if (A.integrator == kIntForestRuth)
+        integrate_fr();
+    else
+        integrate(std::false_type{});
+
+    // ---- dH = sum over exact sites of per-site differences (FP64), and the
+    //      sufficient statistics of the proposal and of the current state ----
+    const double* y2d = A.y2_d + cd.d_off;
+    const double* lrd = A.lrv_d + cd.d_off;
+    constexpr int NTS = 64 * NW;
+    const int gl = wv * kWave + lane;
+    double h0d[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int t = t0 + j;
+        if constexpr (STAGE)
+            h0d[j] = stage[(0 * S + j) * NTS + gl];  // 0 beyond T, as below
+        else
+            h0d[j] = (t < T) ? static_cast<double>(state_at(hc, t, shift)) : 0.0;
+    }
+    double h1_up = static_cast<double>(from_upper(h[0]));
+    double h0_up = from_upper(h0d[0]);
+    if constexpr (NW > 1) {
+        if (lane == 0) {
+            sh.up1[wv] = static_cast<double>(h[0]);
+            sh.up0[wv] = h0d[0];
+        }
+        __syncthreads();
+        if (lane == kWave - 1 && wv < NW - 1) {
+            h1_up = sh.up1[wv + 1];
+            h0_up = sh.up0[wv + 1];
+        }
+    }
+
+    // 1/m_t is read again here rather than kept live across the leapfrog loop
+    const double* minv_again = minv;
+    if constexpr (MASS) asm volatile("" : "+v"(minv_again));
+    double dH = -kin0;
+    double s1[5] = {0, 0, 0, 0, 0}, s0[5] = {0, 0, 0, 0, 0};
+    double sy1 = 0.0, sy0 = 0.0;  // sum y^2 e^{-h} of h' and h
+    double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int t = t0 + j;
+        if (t < td.a || t >= td.b) continue;
+        const double h1 = static_cast<double>(h[j]);
+        const double h0 = h0d[j];
+        const double pj = static_cast<double>(p[j]);
+        const double im = MASS ? minv_again[t] : 1.0;
+        const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
+        double d = 0.5 * pj * pj * im;
+        if (RET) {
+            const double ye0 = (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) * exp_fast(-h0);
+            const double x10 = exp_fast(h0 - h1);  // e^{-h1} / e^{-h0}
+            d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
+            sy1 += ye0 * x10;
+            sy0 += ye0;
+        }
+        if (rv) {
+            const double c = rr - xi;
+            const double e1 = c - h1, e0 = c - h0;
+            d += (e1 - e0) * (e1 + e0) * (0.5 * inv_su);
+        }
+        const double a1 = h1 - mu, a0 = h0 - mu;
+        if (t + 1 < T) {
+            const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + 1]);
+            const double h0n = (j == S - 1) ? h0_up : h0d[j + 1];
+            const double d1 = (h1n - mu) - phi * a1;
+            const double d0 = (h0n - mu) - phi * a0;
+            d += (d1 - d0) * (d1 + d0) * (0.5 * inv_se);
+            s1[2] += a1 * (h1n - mu);
+            s0[2] += a0 * (h0n - mu);
+        }
+        if (t == 0) {
+            d += (1.0 - phi * phi) * (a1 - a0) * (a1 + a0) * (0.5 * inv_se);
+            edge[0] = a1;
+            edge[2] = a0;
+        }
+        if (t == T - 1) {
+            edge[1] = a1;
+            edge[3] = a0;
+        }
+        dH += d;
+        const double e1 = rr - h1 - xi, e0 = rr - h0 - xi;
+        s1[0] += a1; s1[1] += a1 * a1; s1[3] += e1; s1[4] += e1 * e1;
+        s0[0] += a0; s0[1] += a0 * a0; s0[3] += e0; s0[4] += e0 * e0;
+        hp[t] = h[j];
+    }
+
+    double red[kNQ];
+    red[kPartDH] = wave_sum(dH);
+    red[kPartSyProp] = wave_sum(sy1);
+    red[kPartSyCur] = wave_sum(sy0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        red[kPartProp + q] = wave_sum(s1[q]);
+        red[kPartCur + q] = wave_sum(s0[q]);
+    }
+    if constexpr (NW > 1) {
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < kNQ; ++q) sh.red[wv][q] = red[q];
+        }
+        __syncthreads();
+        if (wv == 0) {
+#pragma unroll
+            for (int q = 0; q < kNQ; ++q) {
+                double v = sh.red[0][q];
+                for (int x = 1; x < NW; ++x) v += sh.red[x][q];
+                red[q] = v;
+            }
+        }
+    }
+    if (wv == 0 && lane == 0) {
+        double* out = A.partials + static_cast<int64_t>(tile_id) * kPart;
+#pragma unroll
+        for (int q = 0; q < kNQ; ++q) out[q] = red[q];
+    }
+}
+
+// One launch covers every tile; tiles whose chain ends inside a lane (EDGE)
+// take the variant that substitutes the end-point neighbour per site.
+template <typename R, int S, int NW, bool MASS, bool RET>
+__device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
+    static_assert(S % 4 == 0, "lanes hold whole Philox blocks");
+    static_assert(NW == 1 || NW == 2 || NW == 4 || NW == 8, "tile shapes");
+    // NW = 1: four independent tiles per 256-thread block (no barriers);
+    // NW > 1: one tile per block of NW wavefronts, so a barrier never spans
+    // tiles of chains with different k.
+    constexpr int kTilesPerBlock = NW == 1 ? 4 : 1;
+    using St = Stage<R, S, NW, kTilesPerBlock>;
+    __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
+    __shared__ double stage_all[kTilesPerBlock][St::n];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv_blk = threadIdx.x / kWave;
+    const int w = blockIdx.x * kTilesPerBlock + wv_blk / NW;
+    if (w >= A.n_list) return;  // uniform over the tile's wavefronts
+    const int tile_id = A.tile_first + w;
+    double* stage = stage_all[wv_blk / NW];
+    if (A.tiles[tile_id].edge)
+        traj_tile<R, S, NW, MASS, true, RET, St::on>(A, sh_all[wv_blk / NW], tile_id,
+                                                     wv_blk % NW, lane, stage);
+    else
+        traj_tile<R, S, NW, MASS, false, RET, St::on>(A, sh_all[wv_blk / NW], tile_id,
+                                                      wv_blk % NW, lane, stage);
+}
+
+// Identity mass.
+template <typename R, int S, int NW, bool RET>
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW)
+void k_traj(TrajArgs<R> A) {
+    traj_launch_body<R, S, NW, false, RET>(A);
+}
+
+// Diagonal mass.  Its momentum draw keeps more values live than the leapfrog
+// loop needs; for S <= 8 the register cap of four waves per SIMD moves the
+// overflow to scratch in that once-per-trajectory phase, not in the loop
+// (S = 16 needs more than the cap in the loop itself and is left uncapped).
+template <typename R, int S, int NW, bool RET>
+__global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW)
+__attribute__((amdgpu_waves_per_eu(S <= 8 ? 4 : 1)))
+void k_traj_mass(TrajArgs<R> A) {
+    traj_launch_body<R, S, NW, true, RET>(A);
+}
+
+// ---------------------------------------------------------------------------
+// Statistics of the current state over the exact range of each tile.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_stats(const TileDesc* tiles, int32_t n_tiles,
+                                               const ChainDesc* chains, const rsv_theta* theta,
+                                               const R* h_a, const R* h_b,
+                                               const int32_t* state_sel, const double* shift,
+                                               const double* y2_d, const double* lrv_d,
+                                               double* partials, double* chain_edge) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (w >= n_tiles) return;
+    const TileDesc td = tiles[w];
+    const ChainDesc cd = chains[td.chain];
+    const rsv_theta th = theta[td.chain];
+    const R* hc = (state_sel[td.chain] ? h_b : h_a) + cd.h_off;
+    const double sft = shift ? shift[td.chain] : 0.0;
+    const double* lr = lrv_d + cd.d_off;
+    const double* yy = y2_d + cd.d_off;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = td.a + lane; t < td.b; t += kWave) {
+        const double hv = static_cast<double>(state_at(hc, t, sft));
+        const double b = hv - th.mu;
+        const double e = lr[t] - hv - th.xi;
+        s[0] += b;
+        s[1] += b * b;
+        if (t + 1 < cd.T) s[2] += b * (static_cast<double>(state_at(hc, t + 1, sft)) - th.mu);
+        s[3] += e;
+        s[4] += e * e;
+        s[5] += yy[t] * exp_fast(-hv);
+        if (t == 0) chain_edge[static_cast<int64_t>(td.chain) * kEdge + 2] = b;
+        if (t == cd.T - 1) chain_edge[static_cast<int64_t>(td.chain) * kEdge + 3] = b;
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) partials[static_cast<int64_t>(w) * kPart + kPartCur + q] = s[q];
+        partials[static_cast<int64_t>(w) * kPart + kPartSyCur] = s[5];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// theta update: Gibbs mu -> phi -> sigma_eta^2 -> xi -> sigma_u^2 from the
+// sufficient statistics.  Random numbers come from the theta stream: block 0
+// (z_mu, z_phi, u_phi), block 1 (z_xi), blocks 2..33 and 34..65 the Gamma
+// attempts of sigma_eta^2 and sigma_u^2 (Marsaglia-Tsang, no squeeze; the
+// first accepted attempt is the draw).  None of these depends on the other
+// parameters except through the known Gamma shapes a + T/2, so one lane per
+// block evaluates them all in parallel; one lane then does the algebra.
+// The level move draws from its own stream (tag 4): block 0 (z_c, u_c) and
+// the Gamma(T/2) attempts in blocks 1..32; they follow the theta blocks and
+// the Metropolis uniform in the draw index.
+// ---------------------------------------------------------------------------
+constexpr int kGammaTries = 32;
+constexpr int kGammaEtaBlock = 2, kGammaUBlock = 2 + kGammaTries;
+constexpr int kThetaBlocks = 2 + 2 * kGammaTries;
+constexpr int kAcceptBlock = kThetaBlocks;
+constexpr int kMoveBlock = kThetaBlocks + 1;            // block 0 of the move stream
+constexpr int kMoveGammaBlock = kMoveBlock + 1;         // its Gamma attempts
+constexpr int kDrawBlocks = kMoveGammaBlock + kGammaTries;
+// Gamma attempts evaluated in parallel; the rest only when all of these are
+// rejected (Marsaglia-Tsang accepts > 99% of attempts for shapes >= 1.5).
+// (A build-time knob: the draws do not depend on it, only how many attempts
+// are evaluated before the serial continuation.)
+#ifndef RSV_GAMMA_PARALLEL
+#define RSV_GAMMA_PARALLEL 4
+#endif
+constexpr int kGammaParallel = RSV_GAMMA_PARALLEL;
+
+__device__ inline bool gamma_block(int b) {
+    return (b >= kGammaEtaBlock && b < kThetaBlocks) || b >= kMoveGammaBlock;
+}
+__device__ inline int gamma_index(int b) {  // attempt number within its Gamma draw
+    if (b >= kMoveGammaBlock) return b - kMoveGammaBlock;
+    return b < kGammaUBlock ? b - kGammaEtaBlock : b - kGammaUBlock;
+}
+
+struct ThetaDraws {
+    double z_mu, z_phi, u_phi, z_xi, log_u_accept, z_c, u_c;
+    double g_val[kDrawBlocks];    // d v^3 of each Gamma attempt
+    int g_ok[kDrawBlocks];        // attempt accepted
+};
+
+__device__ void gamma_attempt(int b, ThetaDraws& D, const double u[4], double z0, double shape) {
+#pragma clang fp contract(off)
+    const double d = shape - 1.0 / 3.0;
+    const double cc = 1.0 / sqrt(9.0 * d);
+    double v = 1.0 + cc * z0;
+    int ok = 0;
+    if (v > 0.0) {
+        v = v * v * v;
+        ok = log(u[2]) < 0.5 * z0 * z0 + d - d * v + d * log(v);
+    }
+    D.g_ok[b] = ok;
+    D.g_val[b] = ok ? d * v : d;
+}
+
+// Draw block b for chain c: theta stream blocks, the Metropolis uniform, the
+// level move's blocks.
+__device__ void theta_draw_block(int b, ThetaDraws& D, uint64_t seed, uint64_t sweep, uint64_t c,
+                                 double shape_eta, double shape_u, double shape_level) {
+#pragma clang fp contract(off)
+    double u[4];
+    if (b == kAcceptBlock) {
+        uniforms4(seed, 0, sweep, c, kTagAccept, u);
+        D.log_u_accept = log(u[0]);
+        return;
+    }
+    if (b >= kMoveBlock) {
+        uniforms4(seed, static_cast<uint64_t>(b - kMoveBlock), sweep, c, kTagMove, u);
+        double z0, z1;
+        gauss_pair(u[0], u[1], z0, z1);
+        if (b == kMoveBlock) {
+            D.z_c = z0;
+            D.u_c = u[2];
+        } else {
+            gamma_attempt(b, D, u, z0, shape_level);
+        }
+        return;
+    }
+    uniforms4(seed, static_cast<uint64_t>(b), sweep, c, kTagTheta, u);
+    double z0, z1;
+    gauss_pair(u[0], u[1], z0, z1);
+    if (b == 0) {
+        D.z_mu = z0;
+        D.z_phi = z1;
+        D.u_phi = u[2];
+    } else if (b == 1) {
+        D.z_xi = z0;
+    } else {
+        gamma_attempt(b, D, u, z0, b < kGammaUBlock ? shape_eta : shape_u);
+    }
+}
+
+__device__ double first_gamma(const ThetaDraws& D, int first, bool& ran_out) {
+    for (int i = 0; i < kGammaTries; ++i)
+        if (D.g_ok[first + i]) return D.g_val[first + i];
+    ran_out = true;
+    return D.g_val[first];  // d, the attempt's fallback
+}
+
+// Level move along h -> h + c, mu -> mu + c (xi -> xi - c with the RV term):
+// the return term gives e^{-c} ~ Gamma(T/2, rate S/2) with S = sum y^2 e^{-h},
+// and the prior ratio of mu (and xi) is the Metropolis test; without the
+// return term c is drawn from the Gaussian prior factors.  Returns the c
+// applied (0 when rejected) and moves cur.mu / cur.xi.
+__device__ double level_move(rsv_theta& cur, double S, const rsv_prior& pr, int terms,
+                             const ThetaDraws& D, bool& ran_out) {
+#pragma clang fp contract(off)
+    const bool rv = (terms & RSV_TERM_RV) != 0;
+    double c;
+    bool accept;
+    if (terms & RSV_TERM_RETURN) {
+        const double g = first_gamma(D, kMoveGammaBlock, ran_out);
+        c = -log(2.0 * g / S);
+        const double dm0 = cur.mu - pr.mu_mean, dm1 = cur.mu + c - pr.mu_mean;
+        double log_a = -0.5 * dm1 * dm1 / pr.mu_var - (-0.5 * dm0 * dm0 / pr.mu_var);
+        if (rv) {
+            const double dx0 = cur.xi - pr.xi_mean, dx1 = cur.xi - c - pr.xi_mean;
+            log_a += -0.5 * dx1 * dx1 / pr.xi_var - (-0.5 * dx0 * dx0 / pr.xi_var);
+        }
+        accept = isfinite(c) && log(D.u_c) < log_a;
+    } else {
+        const double prec = 1.0 / pr.mu_var + (rv ? 1.0 / pr.xi_var : 0.0);
+        const double lin = (pr.mu_mean - cur.mu) / pr.mu_var
+                         + (rv ? (cur.xi - pr.xi_mean) / pr.xi_var : 0.0);
+        c = lin / prec + D.z_c / sqrt(prec);
+        accept = true;
+    }
+    if (!accept) return 0.0;
+    cur.mu += c;
+    if (rv) cur.xi -= c;
+    return c;
+}
+
+
+__device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
+                                 const rsv_prior& pr, int terms, const ThetaDraws& D,
+                                 bool& ran_out) {
+#pragma clang fp contract(off)
+    const double B = st[0], B2 = st[1], BB = st[2], D1 = st[3], D2 = st[4];
+    const double bf = st[5], bl = st[6];
+    rsv_theta nxt = cur;
+
+    // mu: Gaussian; precision from the stationary start and T-1 transitions
+    {
+        const double one_m_phi = 1.0 - cur.phi;
+        const double prec = 1.0 / pr.mu_var
+                          + ((1.0 - cur.phi * cur.phi) + (n - 1.0) * one_m_phi * one_m_phi)
+                                / cur.sig2_eta;
+        const double lin = (pr.mu_mean - cur.mu) / pr.mu_var
+                         + ((1.0 - cur.phi * cur.phi) * bf
+                            + one_m_phi * ((B - bf) - cur.phi * (B - bl))) / cur.sig2_eta;
+        nxt.mu = cur.mu + lin / prec + D.z_mu / sqrt(prec);
+    }
+    const double eps = nxt.mu - cur.mu;
+    // a_t = b_t - eps;  Q(phi) = sum a^2 - 2 phi sum a_t a_{t+1} + phi^2 sum_{interior} a^2
+    const double sum_aa = B2 - 2.0 * eps * B + n * eps * eps;
+    const double lag = BB - eps * (2.0 * B - bf - bl) + (n - 1.0) * eps * eps;
+    const double inner = (B2 - bf * bf - bl * bl) - 2.0 * eps * (B - bf - bl) + (n - 2.0) * eps * eps;
+    // phi: independence proposal from the Gaussian factor, corrected by sqrt(1-phi^2)
+    {
+        const double cand = lag / inner + D.z_phi * sqrt(cur.sig2_eta / inner);
+        if (fabs(cand) < 1.0) {
+            const double ratio = (1.0 - cand * cand) / (1.0 - cur.phi * cur.phi);
+            if (D.u_phi * D.u_phi < ratio) nxt.phi = cand;
+        }
+    }
+    {
+        const double q = sum_aa - 2.0 * nxt.phi * lag + nxt.phi * nxt.phi * inner;
+        nxt.sig2_eta = (pr.eta_scale + 0.5 * q) / first_gamma(D, kGammaEtaBlock, ran_out);
+    }
+    if (terms & RSV_TERM_RV) {
+        const double prec = 1.0 / pr.xi_var + n / cur.sig2_u;
+        const double lin = (pr.xi_mean - cur.xi) / pr.xi_var + D1 / cur.sig2_u;
+        nxt.xi = cur.xi + lin / prec + D.z_xi / sqrt(prec);
+        const double f = nxt.xi - cur.xi;
+        const double ss = D2 - 2.0 * f * D1 + n * f * f;
+        nxt.sig2_u = (pr.u_scale + 0.5 * ss) / first_gamma(D, kGammaUBlock, ran_out);
+    }
+    return nxt;
+}
+
+// ---------------------------------------------------------------------------
+// Per-chain finalize: reduce tile partials (compensated, fixed order), the
+// Metropolis test, the choice of statistics, and the theta update.
+// ---------------------------------------------------------------------------
+
+// Everything the finalize does for chain c, by the NT threads of a block
+// (shared scratch passed in); returns in every thread.
+template <int NT>
+__device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[NT / kWave][kNQ],
+                               ThetaDraws& draws) {
+    constexpr int NW = NT / kWave;
+    constexpr int NQ = kNQ;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const ChainDesc cd = A.chains[c];
+
+    // random numbers of this chain's Metropolis test, level move and theta update
+    {
+        const double n = static_cast<double>(cd.T);
+        const bool need_theta = A.do_theta != 0;
+        const bool need_accept = A.do_metropolis && !A.log_u;
+        const bool need_move = A.do_theta && A.level_move;
+        for (int b = tid; b < kDrawBlocks; b += NT) {
+            const bool need = b < kThetaBlocks ? need_theta
+                                               : (b == kAcceptBlock ? need_accept : need_move);
+            if (need && !(gamma_block(b) && gamma_index(b) >= kGammaParallel))
+                theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+        }
+    }
+
+    Comp acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
+    const double* chain_parts = A.partials + static_cast<int64_t>(cd.tile_begin) * kPart;
+    int i = tid;
+    if constexpr (NT >= 256) {
+        // chains of thousands of tiles: the partials of four tiles are loaded
+        // before any is added, so their memory latencies overlap (same order
+        // of additions as one tile at a time)
+        for (; i + 3 * NT < cd.tile_count; i += 4 * NT) {
+            double v[4][NQ];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    v[u][q] = chain_parts[static_cast<int64_t>(i + u * NT) * kPart + q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) comp_add(acc[q], v[u][q]);
+        }
+    }
+    for (; i < cd.tile_count; i += NT) {
+        const double* pp = chain_parts + static_cast<int64_t>(i) * kPart;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
+    }
+    if (tid == 0 && cd.edge_tile >= 0) {
+        const double* pp = A.partials + static_cast<int64_t>(cd.edge_tile) * kPart;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const Comp r = wave_comp_sum(acc[q]);
+        if (lane == 0) part[wv][q] = r;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double tot[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Comp r = part[0][q];
+        for (int w = 1; w < NW; ++w) r = comp_merge(r, part[w][q]);
+        tot[q] = r.s + r.c;
+    }
+
+    // a Gamma draw whose parallel attempts were all rejected continues serially
+    // up to its first accepted attempt, so the first accepted attempt is the
+    // same one a fully parallel evaluation would find
+    {
+        const double n = static_cast<double>(cd.T);
+        const int firsts[3] = {kGammaEtaBlock, kGammaUBlock, kMoveGammaBlock};
+        const bool needed[3] = {A.do_theta != 0, A.do_theta != 0,
+                                A.do_theta && A.level_move != 0};
+        for (int gi = 0; gi < 3; ++gi) {
+            if (!needed[gi]) continue;
+            bool found = false;
+            for (int i = 0; i < kGammaParallel; ++i) found = found || draws.g_ok[firsts[gi] + i];
+            for (int i = kGammaParallel; i < kGammaTries && !found; ++i) {
+                theta_draw_block(firsts[gi] + i, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+                found = draws.g_ok[firsts[gi] + i];
+            }
+        }
+    }
+    const rsv_theta th = A.theta[c];
+    bool use_prop = false;
+    if (A.do_metropolis) {
+#pragma clang fp contract(off)
+        const double dH = tot[kPartDH];
+        const double lu = A.log_u ? A.log_u[c] : draws.log_u_accept;
+        const bool finite = isfinite(dH);
+        const bool accept = finite && (lu < -dH);
+        if (!finite) atomicAdd(&A.counters[kCntNonfiniteDH], 1u);
+        use_prop = accept;
+        if (accept) A.state_sel[c] ^= 1;
+        if (A.delta_h_out) A.delta_h_out[c] = dH;
+        if (A.accepted_out) A.accepted_out[c] = accept ? 1 : 0;
+    }
+    const int base = use_prop ? kPartProp : kPartCur;
+    const double* edge = A.chain_edge + static_cast<int64_t>(c) * kEdge;
+    double st[7];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) st[q] = tot[base + q];
+    st[5] = use_prop ? edge[0] : edge[2];
+    st[6] = use_prop ? edge[1] : edge[3];
+    if (A.stats_out) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) A.stats_out[static_cast<int64_t>(c) * 7 + q] = st[q];
+    }
+    rsv_theta out = th;
+    // the pending level shift belongs to the buffer that held the current state
+    double shift = (A.shift && !use_prop) ? A.shift[c] : 0.0;
+    if (A.do_theta) {
+        bool ran_out = false;
+        rsv_theta cur = th;
+        if (A.level_move) {
+            // h - mu and r - xi - h are unchanged by the move, so the statistics are too
+            const double S = tot[use_prop ? kPartSyProp : kPartSyCur];
+            shift += level_move(cur, S, A.prior, A.terms, draws, ran_out);
+        }
+        out = gibbs_theta(st, static_cast<double>(cd.T), cur, A.prior, A.terms, draws, ran_out);
+        if (ran_out) atomicAdd(&A.counters[kCntGammaExhausted], 1u);
+        A.theta[c] = out;
+    }
+    if (A.shift) A.shift[c] = shift;
+    if (A.theta_trace) A.theta_trace[c] = out;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
+    __shared__ Comp part[NT / kWave][kNQ];
+    __shared__ ThetaDraws draws;
+    finalize_chain<NT>(A, blockIdx.x, part, draws);
+}
+
+// ---------------------------------------------------------------------------
+// Resident sweeps: chains that fit one tile of four wavefronts run all n
+// sweeps (trajectory, dH, Metropolis, theta update, traces) in one launch,
+// one block per chain; the phases are separated by block barriers.
+// ---------------------------------------------------------------------------
+template <typename R, int S, bool MASS, bool RET>
+__global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
+    using St = Stage<R, S, 4, 1>;
+    __shared__ TileShared<R, 4> sh;
+    __shared__ double stage[St::n];
+    __shared__ Comp part[4][kNQ];
+    __shared__ ThetaDraws draws;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const ChainDesc cd = RA.traj.chains[c];
+    const bool edge = cd.edge_tile >= 0;
+    const int tile_id = edge ? cd.edge_tile : cd.tile_begin;
+    const int n_chains = RA.fin.n_chains;
+    for (int i = 0; i < RA.n_sweeps; ++i) {
+        TrajArgs<R> A = RA.traj;
+        A.sweep = RA.first_sweep + static_cast<uint64_t>(i);
+        if (edge)
+            traj_tile<R, S, 4, MASS, true, RET, St::on>(A, sh, tile_id, wv, lane, stage);
+        else
+            traj_tile<R, S, 4, MASS, false, RET, St::on>(A, sh, tile_id, wv, lane, stage);
+        __syncthreads();
+        FinalizeArgs F = RA.fin;
+        F.sweep = A.sweep;
+        const int64_t ofs = static_cast<int64_t>(i) * n_chains;
+        F.delta_h_out = RA.dh_trace ? RA.dh_trace + ofs : nullptr;
+        F.accepted_out = RA.acc_trace ? RA.acc_trace + ofs : nullptr;
+        F.theta_trace = RA.theta_trace ? RA.theta_trace + ofs : nullptr;
+        finalize_chain<256>(F, c, part, draws);
+        __syncthreads();
+        if (RA.h_trace || RA.batch_sum || RA.sq_sum) {
+            const R* src = (RA.traj.state_sel[c] ? RA.traj.h_b : RA.traj.h_a) + cd.h_off;
+            const double sft = RA.fin.shift ? RA.fin.shift[c] : 0.0;
+            R* ht = RA.h_trace ? RA.h_trace + static_cast<int64_t>(i) * RA.n_state + cd.h_off
+                               : nullptr;
+            double* bs = RA.batch_sum
+                             ? RA.batch_sum + static_cast<int64_t>(i / RA.batch_len) * RA.n_state + cd.h_off
+                             : nullptr;
+            double* sq = RA.sq_sum ? RA.sq_sum + cd.h_off : nullptr;
+            for (int t = threadIdx.x; t < cd.T; t += blockDim.x) {
+                const R v = state_at(src, t, sft);
+                if (ht) ht[t] = v;
+                const double vd = static_cast<double>(v);
+                if (bs) bs[t] += vd;
+                if (sq) sq[t] = __builtin_fma(vd, vd, sq[t]);
+            }
+            __syncthreads();
+        }
+    }
+}
+}  // namespace
+
+}  // namespace rsv
+
+#pragma clang diagnostic pop

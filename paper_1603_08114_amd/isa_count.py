@@ -1,6 +1,6 @@
 """Instruction counts of the leapfrog loop, read from the gfx950 assembly.
 
-Compiles csrc/rsv_kernels.hip to device assembly, finds in each trajectory
+Compiles csrc/rsv_traj_f64.hip and csrc/rsv_traj_f32.hip to device assembly, finds in each trajectory
 kernel (identity mass, RSV terms) the loop that carries the DPP
 lane shifts -- one leapfrog step over a lane's S sites -- and counts its VALU
 instructions.  Dividing by S gives VALU instructions per site-update, the
@@ -28,14 +28,17 @@ VARIANTS = {("f64", 4, 1): "IdLi4ELi1ELb1E", ("f64", 4, 2): "IdLi4ELi2ELb1E",
 
 
 def assemble() -> str:
+    text = []
     with tempfile.TemporaryDirectory() as d:
-        out = os.path.join(d, "k.s")
-        cmd = ["hipcc", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, "--cuda-device-only", "-S",
-               os.path.join(B.CSRC, "rsv_kernels.hip"), "-o", out]
-        subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
-        return open(out).read()
+        for src in ("rsv_traj_f64.hip", "rsv_traj_f32.hip"):
+            out = os.path.join(d, src + ".s")
+            cmd = ["hipcc", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                   "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, "--cuda-device-only",
+                   "-S", os.path.join(B.CSRC, src), "-o", out]
+            subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
+            text.append(open(out).read())
+    return "\n".join(text)
 
 
 def kernel_text(asm: str, tag: str) -> str:
