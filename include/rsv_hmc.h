@@ -21,10 +21,22 @@
  *     Python binding passes torch tensors).  The library never allocates or
  *     frees device memory; it works inside the caller's workspace.
  *   - "host" pointers are read during the call only.
- *   - All work is enqueued on the stream given to rsv_hmc_init; calls other
- *     than init, rsv_hmc_check and destroy do not synchronise.
+ *   - All work is enqueued on the stream given to rsv_hmc_init.  Init and
+ *     rsv_hmc_check synchronise; rsv_hmc_momenta, rsv_hmc_trajectory,
+ *     rsv_theta_update and rsv_hmc_sweep first wait for the work already on
+ *     the stream and read the non-finite flag (below), then only enqueue.
  *   - A non-OK status leaves the context usable; rsv_last_error() returns a
  *     thread-local message describing the most recent failure.
+ *   - Non-finite state.  The trajectory kernel flags a non-finite value in
+ *     the current state h or in theta (accepted proposals always have a
+ *     finite dH, so only a caller's write puts one there), and the theta
+ *     update keeps theta unchanged and flags it when its draw would not be
+ *     finite.  rsv_hmc_momenta, rsv_hmc_trajectory, rsv_theta_update and
+ *     rsv_hmc_sweep return RSV_ENONFINITE, enqueuing nothing, while that flag
+ *     is set, so the call after the one whose kernels set it returns it.
+ *     The chains stay at their last accepted state (a trajectory from a
+ *     non-finite state is rejected).  rsv_hmc_check clears the flag once the
+ *     state is finite again.
  *   - One context per stream; a context is not thread-safe.
  *
  * Data layout (HBM)
@@ -247,8 +259,10 @@ rsv_status rsv_hmc_sweep(rsv_ctx *c, uint64_t first_sweep, int32_t n_sweeps,
 
 /* Synchronise the stream and report device-side events since the last
  * check: *n_nonfinite (may be NULL) receives the number of trajectories
- * whose dH was not finite.  Returns RSV_ENONFINITE if the current state of
- * any chain holds a non-finite value, else RSV_OK. */
+ * whose dH was not finite (diverged trajectories, which were rejected).
+ * Recounts the current state: returns RSV_ENONFINITE if any chain holds a
+ * non-finite value, else RSV_OK and clears the non-finite flag that the
+ * other calls report. */
 rsv_status rsv_hmc_check(rsv_ctx *c, int64_t *n_nonfinite);
 
 /* Kernel timing (measurement support).  rsv_hmc_profile allocates

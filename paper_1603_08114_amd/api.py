@@ -224,12 +224,12 @@ class RSVSampler:
         self.log_mass = None
         if log_mass is not None:
             self.log_mass = torch.as_tensor(np.asarray(log_mass, np.float32), **to).contiguous()
+        self.stream = torch.cuda.current_stream(self.device)
         nbytes = rsv_hmc_workspace_bytes(self.pb)
         # 256-byte aligned workspace carved from a uint8 tensor
         self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         shift = (-self._ws_raw.data_ptr()) % 256
         self.workspace = self._ws_raw[shift:shift + nbytes]
-        self.stream = torch.cuda.current_stream(self.device)
         self.ctx = rsv_hmc_init(self.pb, self.h, self.theta, self.log_mass, self.workspace,
                                 self.stream)
 

@@ -347,7 +347,23 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.integrator = (c->pb.flags & RSV_FLAG_OMELYAN)       ? kIntOmelyan
                    : (c->pb.flags & RSV_FLAG_FOREST_RUTH) ? kIntForestRuth
                                                           : kIntLeapfrog;
+    a.counters = c->counters;
     return a;
+}
+
+// A non-finite state or theta found by the kernels of earlier calls: waits
+// for the work already on the stream and reads the flag (4 bytes), so the
+// call after the one whose kernels found it always reports it.
+rsv_status nonfinite_reported(rsv_ctx* c) {
+    uint32_t flag = 0;
+    RSV_HIP(hipMemcpyAsync(&flag, c->counters + kCntNonfiniteState, sizeof flag,
+                           hipMemcpyDeviceToHost, c->stream));
+    RSV_HIP(hipStreamSynchronize(c->stream));
+    if (flag)
+        return fail(RSV_ENONFINITE, "a non-finite value was found in the state or theta; the "
+                                    "chains stay at their last accepted state (rsv_hmc_check "
+                                    "clears this once the state is finite)");
+    return RSV_OK;
 }
 
 template <typename R>
@@ -560,6 +576,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
 
 rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status nf = nonfinite_reported(c); nf != RSV_OK) return nf;
     if (!p_out) return fail(RSV_EINVAL, "p_out is NULL");
     RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T,
                            c->log_mass ? c->mass_sqrt : nullptr, c->pb.seed,
@@ -571,7 +588,9 @@ rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf
                               const double* p0, const double* log_u, double* delta_h,
                               int32_t* accepted) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
-    rsv_status st = ensure_tiles(c, lf);
+    rsv_status st = nonfinite_reported(c);
+    if (st != RSV_OK) return st;
+    st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
     st = run_trajectory(c, sweep, p0, log_u, delta_h, accepted, 0, nullptr, nullptr, nullptr);
     return st != RSV_OK ? st : settle(c);
@@ -579,6 +598,7 @@ rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf
 
 rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
     if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status nf = nonfinite_reported(c); nf != RSV_OK) return nf;
     RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
                          c->h_prop, c->accept, level_moves(c) ? c->shift : nullptr, c->y2_d,
                          c->pb.log_rv, c->partials, c->edge, c->pb.precision));
@@ -594,7 +614,9 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
     if (n_sweeps < 0) return fail(RSV_EINVAL, "n_sweeps must be >= 0");
     if (trace && trace->h_batch_sum && trace->batch_len < 1)
         return fail(RSV_EINVAL, "batch_len must be >= 1 with h_batch_sum");
-    rsv_status st = ensure_tiles(c, lf);
+    rsv_status st = nonfinite_reported(c);
+    if (st != RSV_OK) return st;
+    st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
     const bool timing = c->ev_used < c->ev_start.size();
     if (n_sweeps > 0 && c->single_tile && c->NW == 4 && !timing &&

@@ -20,10 +20,15 @@ namespace rsv {
 // split into its FP64 value and the rounding remainder so that r carries
 // ~1 ulp, P is the degree-10 minimax polynomial for e^r (relative error
 // 3.3e-16 after rounding the coefficients; gen_exp_poly.py), and 2^n is
-// applied by adding n to the exponent field.  n is clamped to [-1022, 1023]:
-// beyond |x| ~ 708 the result is a finite number of the right sign and side
-// (tiny or huge) instead of 0 or inf.  Worst relative error on |x| <= 700:
-// 4.7e-16 (4 ulp).
+// applied by adding n to the exponent field.  n is clamped to [-1022, 1023],
+// so 708 < |x| < 745 gives a finite tiny or huge value of the right side;
+// beyond that the result saturates explicitly: +inf above ln(DBL_MAX), 0
+// below ln of the smallest subnormal, NaN for NaN.  (Without the saturation,
+// arguments past the range of the reduction -- |x| > 2^51, which only a
+// diverged trajectory produces -- would add a meaningless n to the exponent
+// of an infinite polynomial value and return an arbitrary finite number,
+// and dH must be +inf or NaN there so that the proposal is rejected.)
+// Worst relative error on |x| <= 700: 4.7e-16 (4 ulp).
 __device__ __forceinline__ double exp_fast(double x) {
     const double log2e = 0x1.71547652b82fep+0;
     const double ln2_hi = 0x1.62e42fefa39efp-1;
@@ -46,7 +51,10 @@ __device__ __forceinline__ double exp_fast(double x) {
     p = __builtin_fma(p, r, 1.0);
     int ni = __double2loint(t);
     ni = ni < -1022 ? -1022 : (ni > 1023 ? 1023 : ni);
-    return __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
+    const double e = __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
+    // x * inf is +inf for x > 0 and NaN for a NaN x
+    const double hi = x <= 709.782712893384 ? e : x * __builtin_inf();
+    return x < -745.1332191019412 ? 0.0 : hi;
 }
 
 // e^x in FP64 for the leapfrog force only, one instruction shorter than

@@ -79,6 +79,7 @@ struct TrajArgs {
     float* acc_sq;              // starts from, and its square (or nullptr)
     int32_t terms;
     int32_t integrator;         // kIntLeapfrog, kIntOmelyan or kIntForestRuth
+    uint32_t* counters;         // kCntNonfiniteState is set on a non-finite state
 };
 
 struct FinalizeArgs {

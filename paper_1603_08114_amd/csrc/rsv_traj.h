@@ -140,6 +140,17 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             stage[(2 * S + j) * NT + g] = rr;
         }
     }
+    // a non-finite value in the current state (written by the caller, since
+    // accepted proposals always have a finite dH) or in theta is flagged for
+    // the host, which reports it at its next call; the trajectory still runs
+    // and is rejected (its dH is not finite), so the state does not change
+    {
+        bool bad = !(isfinite(phi) && isfinite(mu) && isfinite(xi) && isfinite(inv_se));
+#pragma unroll
+        for (int j = 0; j < S; ++j) bad = bad || !isfinite(static_cast<double>(h[j]));
+        const uint64_t any_bad = __ballot(bad);
+        if (any_bad != 0 && lane == 0) atomicOr(&A.counters[kCntNonfiniteState], 1u);
+    }
     // batch-means accumulators of the starting state (the previous sweep's
     // result) on the exact sites: the read-modify-writes overlap with the
     // momentum draw instead of costing a separate pass over the state
@@ -752,6 +763,105 @@ __device__ rsv_theta gibbs_theta(const double st[7], double n, rsv_theta cur,
 // Metropolis test, the choice of statistics, and the theta update.
 // ---------------------------------------------------------------------------
 
+// Random numbers of chain c's Metropolis test, level move and theta update,
+// by `nt` lanes (lane `tid` evaluates blocks tid, tid + nt, ...); the Gamma
+// attempts beyond the first kGammaParallel wait for finalize_decide.
+__device__ void finalize_draws(const FinalizeArgs& A, const int c, const int T, const int tid,
+                               const int nt, ThetaDraws& draws) {
+    const double n = static_cast<double>(T);
+    const bool need_theta = A.do_theta != 0;
+    const bool need_accept = A.do_metropolis && !A.log_u;
+    const bool need_move = A.do_theta && A.level_move;
+    for (int b = tid; b < kDrawBlocks; b += nt) {
+        const bool need = b < kThetaBlocks ? need_theta
+                                           : (b == kAcceptBlock ? need_accept : need_move);
+        if (need && !(gamma_block(b) && gamma_index(b) >= kGammaParallel))
+            theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                             A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+    }
+}
+
+// What the finalize decided for one chain.
+struct Decision {
+    bool accepted;
+    double shift;   // the chain's pending level shift after this sweep
+};
+
+// Metropolis test, statistics and theta update of chain c from its totals
+// tot[kNQ] (dH, statistics of h' and h, S of h' and h) and edge values
+// edge[kEdge], by one lane.  shift_in is the pending level shift of the
+// current state.  Writes theta, the per-chain outputs and counters of A.
+__device__ Decision finalize_decide(const FinalizeArgs& A, const int c, const int T,
+                                    const double (&tot)[kNQ], const double (&edge)[kEdge],
+                                    double shift_in, ThetaDraws& draws) {
+    // a Gamma draw whose parallel attempts were all rejected continues serially
+    // up to its first accepted attempt, so the first accepted attempt is the
+    // same one a fully parallel evaluation would find
+    {
+        const double n = static_cast<double>(T);
+        const int firsts[3] = {kGammaEtaBlock, kGammaUBlock, kMoveGammaBlock};
+        const bool needed[3] = {A.do_theta != 0, A.do_theta != 0,
+                                A.do_theta && A.level_move != 0};
+        for (int gi = 0; gi < 3; ++gi) {
+            if (!needed[gi]) continue;
+            bool found = false;
+            for (int i = 0; i < kGammaParallel; ++i) found = found || draws.g_ok[firsts[gi] + i];
+            for (int i = kGammaParallel; i < kGammaTries && !found; ++i) {
+                theta_draw_block(firsts[gi] + i, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
+                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
+                found = draws.g_ok[firsts[gi] + i];
+            }
+        }
+    }
+    const rsv_theta th = A.theta[c];
+    bool use_prop = false;
+    if (A.do_metropolis) {
+#pragma clang fp contract(off)
+        const double dH = tot[kPartDH];
+        const double lu = A.log_u ? A.log_u[c] : draws.log_u_accept;
+        const bool finite = isfinite(dH);
+        const bool accept = finite && (lu < -dH);
+        if (!finite) atomicAdd(&A.counters[kCntNonfiniteDH], 1u);
+        use_prop = accept;
+        if (A.delta_h_out) A.delta_h_out[c] = dH;
+        if (A.accepted_out) A.accepted_out[c] = accept ? 1 : 0;
+    }
+    const int base = use_prop ? kPartProp : kPartCur;
+    double st[7];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) st[q] = tot[base + q];
+    st[5] = use_prop ? edge[0] : edge[2];
+    st[6] = use_prop ? edge[1] : edge[3];
+    if (A.stats_out) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) A.stats_out[static_cast<int64_t>(c) * 7 + q] = st[q];
+    }
+    rsv_theta out = th;
+    // the pending level shift belongs to the buffer that held the current state
+    double shift = use_prop ? 0.0 : shift_in;
+    if (A.do_theta) {
+        bool ran_out = false;
+        rsv_theta cur = th;
+        if (A.level_move) {
+            // h - mu and r - xi - h are unchanged by the move, so the statistics are too
+            const double S = tot[use_prop ? kPartSyProp : kPartSyCur];
+            shift += level_move(cur, S, A.prior, A.terms, draws, ran_out);
+        }
+        out = gibbs_theta(st, static_cast<double>(T), cur, A.prior, A.terms, draws, ran_out);
+        if (ran_out) atomicAdd(&A.counters[kCntGammaExhausted], 1u);
+        if (!(isfinite(out.phi) && isfinite(out.mu) && isfinite(out.xi) &&
+              isfinite(out.sig2_eta) && isfinite(out.sig2_u))) {
+            // statistics of a non-finite state: keep theta and the level, flag it
+            atomicOr(&A.counters[kCntNonfiniteState], 1u);
+            out = th;
+            shift = use_prop ? 0.0 : shift_in;
+        }
+        A.theta[c] = out;
+    }
+    if (A.theta_trace) A.theta_trace[c] = out;
+    return Decision{use_prop, shift};
+}
+
 // Everything the finalize does for chain c, by the NT threads of a block
 // (shared scratch passed in); returns in every thread.
 template <int NT>
@@ -764,20 +874,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
     const int wv = tid / kWave;
     const ChainDesc cd = A.chains[c];
 
-    // random numbers of this chain's Metropolis test, level move and theta update
-    {
-        const double n = static_cast<double>(cd.T);
-        const bool need_theta = A.do_theta != 0;
-        const bool need_accept = A.do_metropolis && !A.log_u;
-        const bool need_move = A.do_theta && A.level_move;
-        for (int b = tid; b < kDrawBlocks; b += NT) {
-            const bool need = b < kThetaBlocks ? need_theta
-                                               : (b == kAcceptBlock ? need_accept : need_move);
-            if (need && !(gamma_block(b) && gamma_index(b) >= kGammaParallel))
-                theta_draw_block(b, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
-                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
-        }
-    }
+    finalize_draws(A, c, cd.T, tid, NT, draws);
 
     Comp acc[NQ];
 #pragma unroll
@@ -825,68 +922,12 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         for (int w = 1; w < NW; ++w) r = comp_merge(r, part[w][q]);
         tot[q] = r.s + r.c;
     }
-
-    // a Gamma draw whose parallel attempts were all rejected continues serially
-    // up to its first accepted attempt, so the first accepted attempt is the
-    // same one a fully parallel evaluation would find
-    {
-        const double n = static_cast<double>(cd.T);
-        const int firsts[3] = {kGammaEtaBlock, kGammaUBlock, kMoveGammaBlock};
-        const bool needed[3] = {A.do_theta != 0, A.do_theta != 0,
-                                A.do_theta && A.level_move != 0};
-        for (int gi = 0; gi < 3; ++gi) {
-            if (!needed[gi]) continue;
-            bool found = false;
-            for (int i = 0; i < kGammaParallel; ++i) found = found || draws.g_ok[firsts[gi] + i];
-            for (int i = kGammaParallel; i < kGammaTries && !found; ++i) {
-                theta_draw_block(firsts[gi] + i, draws, A.seed, A.sweep, static_cast<uint64_t>(c),
-                                 A.prior.eta_shape + 0.5 * n, A.prior.u_shape + 0.5 * n, 0.5 * n);
-                found = draws.g_ok[firsts[gi] + i];
-            }
-        }
-    }
-    const rsv_theta th = A.theta[c];
-    bool use_prop = false;
-    if (A.do_metropolis) {
-#pragma clang fp contract(off)
-        const double dH = tot[kPartDH];
-        const double lu = A.log_u ? A.log_u[c] : draws.log_u_accept;
-        const bool finite = isfinite(dH);
-        const bool accept = finite && (lu < -dH);
-        if (!finite) atomicAdd(&A.counters[kCntNonfiniteDH], 1u);
-        use_prop = accept;
-        if (accept) A.state_sel[c] ^= 1;
-        if (A.delta_h_out) A.delta_h_out[c] = dH;
-        if (A.accepted_out) A.accepted_out[c] = accept ? 1 : 0;
-    }
-    const int base = use_prop ? kPartProp : kPartCur;
-    const double* edge = A.chain_edge + static_cast<int64_t>(c) * kEdge;
-    double st[7];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) st[q] = tot[base + q];
-    st[5] = use_prop ? edge[0] : edge[2];
-    st[6] = use_prop ? edge[1] : edge[3];
-    if (A.stats_out) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) A.stats_out[static_cast<int64_t>(c) * 7 + q] = st[q];
-    }
-    rsv_theta out = th;
-    // the pending level shift belongs to the buffer that held the current state
-    double shift = (A.shift && !use_prop) ? A.shift[c] : 0.0;
-    if (A.do_theta) {
-        bool ran_out = false;
-        rsv_theta cur = th;
-        if (A.level_move) {
-            // h - mu and r - xi - h are unchanged by the move, so the statistics are too
-            const double S = tot[use_prop ? kPartSyProp : kPartSyCur];
-            shift += level_move(cur, S, A.prior, A.terms, draws, ran_out);
-        }
-        out = gibbs_theta(st, static_cast<double>(cd.T), cur, A.prior, A.terms, draws, ran_out);
-        if (ran_out) atomicAdd(&A.counters[kCntGammaExhausted], 1u);
-        A.theta[c] = out;
-    }
-    if (A.shift) A.shift[c] = shift;
-    if (A.theta_trace) A.theta_trace[c] = out;
+    const double* ce = A.chain_edge + static_cast<int64_t>(c) * kEdge;
+    const double edge[kEdge] = {ce[0], ce[1], ce[2], ce[3]};
+    const double shift_in = A.shift ? A.shift[c] : 0.0;
+    const Decision d = finalize_decide(A, c, cd.T, tot, edge, shift_in, draws);
+    if (d.accepted) A.state_sel[c] ^= 1;
+    if (A.shift) A.shift[c] = d.shift;
 }
 
 template <int NT>

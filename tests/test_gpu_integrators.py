@@ -20,8 +20,9 @@ from paper_1603_08114_amd import api  # noqa: E402
 from paper_1603_08114_amd._lib import (RSV_F32_MIXED, RSV_FLAG_FOREST_RUTH,  # noqa: E402
                                        RSV_FLAG_LEVEL_MOVE, RSV_FLAG_NO_RESIDENT,
                                        RSV_FLAG_OMELYAN)
-from test_gpu_parity import (NEAR_TIE, TH, _compare_runs, chain_slices,  # noqa: E402
-                             make_series, rel_inf, sampler, state_from)
+from _parity import sweeps_with_resync  # noqa: E402
+from test_gpu_parity import (NEAR_TIE, TH, _resync_builder, chain_slices,  # noqa: E402
+                             make_series, oracle_ref, rel_inf, sampler, state_from)
 
 OM = oracle.INT_OMELYAN
 FR = oracle.INT_FOREST_RUTH
@@ -136,21 +137,21 @@ def test_sweeps_match_oracle(flags, j, name):
     if name == "forest_ruth":
         k, dt = 7, 0.05
     thetas = synth.draw_batch_thetas(len(Ts), 8)
-    smp, offsets, ys, rs, h0, th = sampler(Ts, C, k=k, thetas=thetas, dtau_jitter=j,
-                                           flags=flags | flag)
-    out = smp.sweep(30, n, (k, dt), update_theta=True)
-    acc = out["accepted"].cpu().numpy()
-    dh = out["delta_h"].cpu().numpy()
-    tht = out["theta"].cpu().numpy()
-    h_end = smp.h.cpu().numpy()
+    offsets, ys, rs, hs = make_series(Ts, 105, thetas)
+    h0 = state_from(hs, C, 0.05)
+    th = [thetas[s] for s in range(len(Ts)) for _ in range(C)]
     moves = oracle.MOVE_LEVEL if flags & RSV_FLAG_LEVEL_MOVE else 0
-    for c, (s, sl) in enumerate(chain_slices(offsets, C)):
-        ref = oracle.run(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, seed=smp.pb.seed,
-                         chain=c, first_sweep=30, jitter=j, moves=moves, integrator=integ)
-        m = _compare_runs(acc[:, c], dh[:, c], tht[:, c], ref, smp.pb.seed, c, 30)
-        if m == n:
-            assert rel_inf(h_end[sl], ref["h"]) <= 1e-10
-    assert acc.mean() > 0.5
+    slices = [sl for _, sl in chain_slices(offsets, C)]
+    refs = [oracle_ref(h0[sl], th[c], ys[s] ** 2, rs[s], k, dt, n, 30, seed=5, chain=c,
+                       jitter=j, moves=moves, integrator=integ)
+            for c, (s, sl) in enumerate(chain_slices(offsets, C))]
+    build = _resync_builder(offsets, ys, rs, C, 5, k, dtau_jitter=j, flags=flags | flag)
+    n_ties, smp = sweeps_with_resync(build, h0, th, slices, refs, 5, 30, n, (k, dt))
+    if smp is not None:
+        h_end = smp.h.cpu().numpy()
+        for c, sl in enumerate(slices):
+            assert rel_inf(h_end[sl], refs[c]["h"]) <= 1e-10
+    assert np.mean([r["accepted"].mean() for r in refs]) > 0.5
 
 
 @pytest.mark.parametrize("precision", [0, RSV_F32_MIXED])

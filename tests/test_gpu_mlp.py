@@ -1,6 +1,7 @@
 """Parity of the BF16-MFMA mass network kernels with the FP64 oracle that
 emulates their rounding points (oracle/mlp_oracle.py).  Bars: forward
-elementwise rel <= 1e-2, norm rel <= 1e-3; gradient norm rel <= 1e-2;
+elementwise rel <= 1e-2, norm rel <= 1e-3; gradient norm rel <= 1e-3 and
+elementwise rel <= 1e-2 above a floor of 1e-3 of each block's largest entry;
 Adam rel <= 1e-5 (FP32 vs FP64); features equal except rare last-bit
 differences of the bfloat16 rounding (FP64 log on both sides)."""
 import numpy as np
@@ -90,7 +91,23 @@ def test_gradient_matches_oracle(n, use_rows):
     g, loss = net.gradient(xg, tg, rows)
     ref = M.flatten(M.grad(p, Xb[sel], target.astype(np.float32).astype(np.float64)[sel], bf16=True))
     got = g.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref), np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"gradient: norm rel err {err:.2e}")
+    assert err <= 1e-3, err
+    # elementwise within each parameter block, above a floor of 1e-3 of the
+    # block's largest entry (smaller entries are sums that cancel to below the
+    # FP32 accumulation error of their terms)
+    i = 0
+    for name, shape in M.PARAM_SHAPES:
+        n_el = int(np.prod(shape))
+        r, gv = ref[i:i + n_el], got[i:i + n_el]
+        i += n_el
+        floor = 1e-3 * np.max(np.abs(r)) if np.any(r) else 1e-30
+        big = np.abs(r) >= floor
+        rel = np.abs(gv[big] - r[big]) / np.abs(r[big])
+        print(f"  {name}: {big.sum()}/{n_el} entries above floor, max rel err {rel.max():.2e}")
+        assert rel.max() <= 1e-2, (name, rel.max())
+        assert np.all(np.abs(gv[~big] - r[~big]) <= 1e-2 * floor + 1e-5 * np.max(np.abs(r))), name
     ref_loss = M.loss(p, Xb[sel], target.astype(np.float32).astype(np.float64)[sel], bf16=True)
     assert loss.item() == pytest.approx(ref_loss, rel=1e-4)
     # padding rows of W1 get no gradient
