@@ -218,6 +218,25 @@ rsv_status rsv_hmc_init(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta
                         const float *log_mass, void *workspace, size_t ws_bytes,
                         void *hip_stream);
 
+/* rsv_hmc_init for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same context, but its workspace is a library-owned device array of
+ * RSV_STATIC_WORKSPACE_BYTES (32 MiB) on the device current at the call,
+ * which that device keeps until the process ends.  Nothing is allocated on
+ * the device here or in later calls on the context.  Limit: problems whose
+ * rsv_hmc_workspace_bytes exceeds RSV_STATIC_WORKSPACE_BYTES get
+ * RSV_ENOMEM (e.g. one FP64 chain of more than about 830 000 sites).
+ * Sharing: every static context on a device uses that device's one array,
+ * and each rsv_hmc_init_static takes it over: calls on an older static
+ * context of the device then return RSV_ESTATE.  The array keeps the last
+ * context's contents; initialisation clears what must start at zero.  Work
+ * of an older static context still running when a new one is created races
+ * with it: synchronise that context's stream first.  Other arguments and
+ * errors as rsv_hmc_init. */
+#define RSV_STATIC_WORKSPACE_BYTES (32u << 20)
+rsv_status rsv_hmc_init_static(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta *theta,
+                               const float *log_mass, void *hip_stream);
+
 /* Momentum refresh of sweep `sweep` (the Gibbs draw p ~ N(0, m) implied by
  * the kinetic term of H, Sec. 3), written to p_out (device, FP64, one entry
  * per state entry).  The trajectory of that sweep starts from exactly these

@@ -18,13 +18,15 @@ RSV_FLAG_NO_RESIDENT = 1
 RSV_FLAG_LEVEL_MOVE = 2
 RSV_FLAG_OMELYAN = 4
 RSV_FLAG_FOREST_RUTH = 8
+RSV_STATIC_WORKSPACE_BYTES = 32 << 20
 
 THETA_KEYS = ("phi", "mu", "xi", "sig2_eta", "sig2_u")
 PRIOR_KEYS = ("mu_mean", "mu_var", "xi_mean", "xi_var",
               "eta_shape", "eta_scale", "u_shape", "u_scale")
 
 # Every symbol include/rsv_hmc.h declares.
-EXPORTS = ("rsv_hmc_workspace_bytes", "rsv_hmc_state_size", "rsv_hmc_init", "rsv_hmc_momenta",
+EXPORTS = ("rsv_hmc_workspace_bytes", "rsv_hmc_state_size", "rsv_hmc_init",
+           "rsv_hmc_init_static", "rsv_hmc_momenta",
            "rsv_hmc_trajectory", "rsv_theta_update", "rsv_hmc_sweep", "rsv_hmc_check",
            "rsv_hmc_profile", "rsv_hmc_kernel_time", "rsv_hmc_destroy", "rsv_last_error",
            "rsv_mlp_features", "rsv_mlp_forward", "rsv_mlp_grad_workspace_bytes", "rsv_mlp_grad",
@@ -80,6 +82,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "rsv_hmc_workspace_bytes": (C.c_size_t, [P(rsv_problem)]),
         "rsv_hmc_state_size": (C.c_int64, [P(rsv_problem)]),
         "rsv_hmc_init": (C.c_int32, [P(V), P(rsv_problem), V, V, V, V, C.c_size_t, V]),
+        "rsv_hmc_init_static": (C.c_int32, [P(V), P(rsv_problem), V, V, V, V]),
         "rsv_hmc_momenta": (C.c_int32, [V, C.c_uint64, V]),
         "rsv_hmc_trajectory": (C.c_int32, [V, C.c_uint64, P(rsv_leapfrog), V, V, V, V]),
         "rsv_theta_update": (C.c_int32, [V, C.c_uint64, V]),

@@ -140,6 +140,16 @@ def rsv_hmc_init(pb: Problem, h: torch.Tensor, theta: torch.Tensor,
     return ctx
 
 
+def rsv_hmc_init_static(pb: Problem, h: torch.Tensor, theta: torch.Tensor,
+                        log_mass: Optional[torch.Tensor],
+                        stream: Optional[torch.cuda.Stream] = None) -> C.c_void_p:
+    ctx = C.c_void_p()
+    st = lib().rsv_hmc_init_static(C.byref(ctx), C.byref(pb.struct()), _ptr(h), _ptr(theta),
+                                   _ptr(log_mass), _stream_handle(stream))
+    _check(st, "rsv_hmc_init_static")
+    return ctx
+
+
 def rsv_hmc_momenta(ctx, sweep: int, p_out: torch.Tensor):
     _check(lib().rsv_hmc_momenta(ctx, int(sweep), _ptr(p_out)), "rsv_hmc_momenta")
 
@@ -203,7 +213,7 @@ class RSVSampler:
     def __init__(self, offsets, y, log_rv, h0, theta0, chains_per_series=1,
                  precision=L.RSV_F64, terms=L.RSV_TERMS_RSV, max_steps=50, seed=0,
                  prior=None, log_mass=None, sites_per_lane=0, waves_per_tile=0, flags=0,
-                 dtau_jitter=0.0, device="cuda"):
+                 dtau_jitter=0.0, device="cuda", static_workspace=False):
         if not torch.cuda.is_available():
             raise RuntimeError("RSVSampler needs a GPU (HIP device)")
         self.device = torch.device(device)
@@ -225,6 +235,11 @@ class RSVSampler:
         if log_mass is not None:
             self.log_mass = torch.as_tensor(np.asarray(log_mass, np.float32), **to).contiguous()
         self.stream = torch.cuda.current_stream(self.device)
+        if static_workspace:  # the library's own device array (rsv_hmc_init_static)
+            self.workspace = None
+            self.ctx = rsv_hmc_init_static(self.pb, self.h, self.theta, self.log_mass,
+                                           self.stream)
+            return
         nbytes = rsv_hmc_workspace_bytes(self.pb)
         # 256-byte aligned workspace carved from a uint8 tensor
         self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -208,6 +209,10 @@ struct rsv_ctx {
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     Layout lay;
+    // contexts of rsv_hmc_init_static: the device whose static workspace they
+    // use and the generation they hold (-1: the caller's workspace)
+    int static_dev = -1;
+    uint64_t static_gen = 0;
     // device views into the workspace
     double* y2_d = nullptr;
     float* y2_f = nullptr;
@@ -239,6 +244,35 @@ struct rsv_ctx {
         for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
     }
 };
+
+// ---------------------------------------------------------------------------
+// Static workspace of rsv_hmc_init_static: one array per device, taken by the
+// newest static context on that device.  In host code `scratch` names a
+// host-side stand-in; its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is passed to kernels and copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[RSV_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+std::mutex g_static_mu;
+std::vector<void*> g_static_ptr;     // per device: device address of `scratch`
+std::vector<uint64_t> g_static_gen;  // per device: generation of the newest static context
+
+// A context may be used: not NULL, and (for a static context) still the
+// newest static context of its device.
+rsv_status usable(const rsv_ctx* c) {
+    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_gen[c->static_dev] != c->static_gen)
+            return fail(RSV_ESTATE, "this static-workspace context was superseded by a newer "
+                                    "rsv_hmc_init_static on device %d", c->static_dev);
+    }
+    return RSV_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -574,8 +608,49 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     return RSV_OK;
 }
 
+rsv_status rsv_hmc_init_static(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
+                               const float* log_mass, void* hip_stream) {
+    if (!out) return fail(RSV_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    rsv_status st = make_layout(pb, &L);
+    if (st != RSV_OK) return st;
+    if (L.total > RSV_STATIC_WORKSPACE_BYTES)
+        return fail(RSV_ENOMEM, "the problem needs %zu bytes of workspace; the static workspace "
+                                "holds %zu (use rsv_hmc_init with a caller workspace)",
+                    L.total, static_cast<size_t>(RSV_STATIC_WORKSPACE_BYTES));
+    int dev = 0;
+    RSV_HIP(hipGetDevice(&dev));
+    void* ws = nullptr;
+    uint64_t gen = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (static_cast<size_t>(dev) >= g_static_ptr.size()) {
+            g_static_ptr.resize(dev + 1, nullptr);
+            g_static_gen.resize(dev + 1, 0);
+        }
+        if (!g_static_ptr[dev]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(RSV_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                            hipGetErrorString(e));
+            g_static_ptr[dev] = p;
+        }
+        ws = g_static_ptr[dev];
+        // from here on the array is this context's; an older static context
+        // on the device is refused even if this initialisation fails
+        gen = ++g_static_gen[dev];
+    }
+    st = rsv_hmc_init(out, pb, h, theta, log_mass, ws, RSV_STATIC_WORKSPACE_BYTES, hip_stream);
+    if (st != RSV_OK) return st;
+    (*out)->static_dev = dev;
+    (*out)->static_gen = gen;
+    return RSV_OK;
+}
+
 rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     if (rsv_status nf = nonfinite_reported(c); nf != RSV_OK) return nf;
     if (!p_out) return fail(RSV_EINVAL, "p_out is NULL");
     RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T,
@@ -587,7 +662,7 @@ rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
 rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf,
                               const double* p0, const double* log_u, double* delta_h,
                               int32_t* accepted) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     rsv_status st = nonfinite_reported(c);
     if (st != RSV_OK) return st;
     st = ensure_tiles(c, lf);
@@ -597,7 +672,7 @@ rsv_status rsv_hmc_trajectory(rsv_ctx* c, uint64_t sweep, const rsv_leapfrog* lf
 }
 
 rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     if (rsv_status nf = nonfinite_reported(c); nf != RSV_OK) return nf;
     RSV_HIP(launch_stats(c->stream, c->tiles, c->n_body + c->n_edge, c->chains, c->theta, c->h,
                          c->h_prop, c->accept, level_moves(c) ? c->shift : nullptr, c->y2_d,
@@ -610,7 +685,7 @@ rsv_status rsv_theta_update(rsv_ctx* c, uint64_t sweep, double* suff_stats) {
 
 rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
                          const rsv_leapfrog* lf, int32_t update_theta, const rsv_trace* trace) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     if (n_sweeps < 0) return fail(RSV_EINVAL, "n_sweeps must be >= 0");
     if (trace && trace->h_batch_sum && trace->batch_len < 1)
         return fail(RSV_EINVAL, "batch_len must be >= 1 with h_batch_sum");
@@ -673,7 +748,7 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
 }
 
 rsv_status rsv_hmc_check(rsv_ctx* c, int64_t* n_nonfinite) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     RSV_HIP(hipMemsetAsync(c->counters + kCntNonfiniteState, 0, sizeof(uint32_t), c->stream));
     RSV_HIP(launch_count_nonfinite(c->stream, c->h, c->n_state, c->pb.precision,
                                    c->counters + kCntNonfiniteState));
@@ -688,7 +763,7 @@ rsv_status rsv_hmc_check(rsv_ctx* c, int64_t* n_nonfinite) {
 }
 
 rsv_status rsv_hmc_profile(rsv_ctx* c, int32_t max_records) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     if (max_records < 0) return fail(RSV_EINVAL, "max_records must be >= 0");
     for (hipEvent_t e : c->ev_start) RSV_HIP(hipEventDestroy(e));
     for (hipEvent_t e : c->ev_stop) RSV_HIP(hipEventDestroy(e));
@@ -706,7 +781,7 @@ rsv_status rsv_hmc_profile(rsv_ctx* c, int32_t max_records) {
 }
 
 rsv_status rsv_hmc_kernel_time(rsv_ctx* c, double* total_ms, int64_t* n_records) {
-    if (!c) return fail(RSV_ESTATE, "context is NULL");
+    if (rsv_status u = usable(c); u != RSV_OK) return u;
     double sum = 0.0;
     if (c->ev_used > 0) RSV_HIP(hipEventSynchronize(c->ev_stop[c->ev_used - 1]));
     for (size_t i = 0; i < c->ev_used; ++i) {

@@ -118,3 +118,17 @@ def test_autotune_cache_key_buckets():
     assert autotune.cache_key(1, 30, [0, 700, 1500], 4) != a
     assert autotune.cache_key(0, 20, [0, 700, 1500], 4) != a
     assert {S for S, _ in autotune.SHAPES[_lib.RSV_F64]} == {4, 8}
+
+
+def test_static_workspace_limit_checked_on_the_host():
+    """rsv_hmc_init_static refuses a problem whose workspace exceeds the
+    static array before any device call (no GPU needed)."""
+    big = _pb([0, 900_000], max_steps=50)
+    assert api.rsv_hmc_workspace_bytes(big) > _lib.RSV_STATIC_WORKSPACE_BYTES
+    ctx = C.c_void_p()
+    st = api.lib().rsv_hmc_init_static(C.byref(ctx), C.byref(big.struct()), None, None, None,
+                                       None)
+    assert st == _lib.RSV_ENOMEM and not ctx.value
+    assert b"static workspace" in api.lib().rsv_last_error()
+    small = _pb([0, 1000], max_steps=20)
+    assert api.rsv_hmc_workspace_bytes(small) < _lib.RSV_STATIC_WORKSPACE_BYTES

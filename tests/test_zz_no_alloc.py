@@ -1,0 +1,78 @@
+"""rsv_hmc_init_static: a context whose workspace is the library's static
+device array (no device allocation), against the same problem on a caller
+workspace (rsv_hmc_init).  Two contexts in a row on the device, the second
+with a smaller problem; every per-sweep record and the final state must be
+identical (same kernels, same arithmetic, same random streams)."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1603_08114_amd import api  # noqa: E402
+from paper_1603_08114_amd._lib import (RSV_ENOMEM, RSV_ESTATE, RSV_F32_MIXED,  # noqa: E402
+                                       RSV_F64, RSV_FLAG_NO_RESIDENT)
+
+
+def _problem(Ts, C, seed):
+    thetas = synth.draw_batch_thetas(len(Ts), seed)
+    ys, rs, hs = [], [], []
+    for i, T in enumerate(Ts):
+        y, r, h = synth.simulate_rsv_long(T, thetas[i], seed + 31 * i)
+        ys.append(y); rs.append(r); hs.append(h)
+    offsets = np.concatenate([[0], np.cumsum(Ts)]).astype(np.int64)
+    h0 = np.concatenate([h for h in hs for _ in range(C)])
+    th = [thetas[s] for s in range(len(Ts)) for _ in range(C)]
+    return offsets, np.concatenate(ys), np.concatenate(rs), h0, th
+
+
+def _run(static, offsets, y, r, h0, th, C, precision, flags, k, dt, n):
+    smp = api.RSVSampler(offsets, y, r, h0, th, chains_per_series=C, precision=precision,
+                         max_steps=k, seed=11, flags=flags, static_workspace=static)
+    out = smp.sweep(0, n, (k, dt), update_theta=True, record_h=True, batch_len=5)
+    torch.cuda.synchronize()
+    out["state"] = smp.h.clone()
+    out["theta_end"] = smp.theta.clone()
+    return smp, out
+
+
+def _assert_same(a, b):
+    for key in ("delta_h", "accepted", "theta", "h", "h_batch_sum", "h_sq_sum", "state",
+                "theta_end"):
+        x, y = a[key], b[key]
+        if x.is_floating_point():
+            assert torch.equal(x.isnan(), y.isnan()), key
+            x, y = x.nan_to_num(nan=0.0), y.nan_to_num(nan=0.0)
+        assert torch.equal(x, y), key
+
+
+@pytest.mark.parametrize("precision,flags", [(RSV_F64, 0), (RSV_F32_MIXED, RSV_FLAG_NO_RESIDENT)])
+def test_static_workspace_matches_caller_workspace(precision, flags):
+    k, dt, n = 12, 0.04, 25
+    # first call: several tiles per chain (per-kernel path), two chains per series
+    big = _problem([5000, 2300, 700], 2, 3)
+    s_big, o_big = _run(True, *big, 2, precision, flags, k, dt, n)
+    _, r_big = _run(False, *big, 2, precision, flags, k, dt, n)
+    _assert_same(o_big, r_big)
+    # second call, smaller problem, on the same (reused) array
+    small = _problem([900], 1, 4)
+    s_small, o_small = _run(True, *small, 1, precision, flags, k, dt, n)
+    _, r_small = _run(False, *small, 1, precision, flags, k, dt, n)
+    _assert_same(o_small, r_small)
+    # the first static context lost the array to the second
+    with pytest.raises(api.RSVError) as e:
+        s_big.sweep(n, 1, (k, dt))
+    assert e.value.status == RSV_ESTATE
+    s_small.sweep(n, 1, (k, dt))  # the newest one still works
+    torch.cuda.synchronize()
+
+
+def test_static_workspace_rejects_a_problem_beyond_its_size():
+    T = 900_000  # FP64: about 35 MiB of workspace, more than the 32 MiB array
+    y, r, h = synth.simulate_rsv_long(T, synth.THETA_STAR, 1)
+    with pytest.raises(api.RSVError) as e:
+        api.RSVSampler([0, T], y, r, h, synth.THETA_STAR, max_steps=50, static_workspace=True)
+    assert e.value.status == RSV_ENOMEM
+    assert "static workspace" in str(e.value)
