@@ -79,11 +79,16 @@ typedef enum { RSV_F64 = 0, RSV_F32_MIXED = 1 } rsv_precision;
 enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
 
 /* Flags.
- * RSV_FLAG_NO_RESIDENT: by default rsv_hmc_sweep runs every sweep of a call
- *   in a single launch when each chain fits one tile of four wavefronts (the
- *   chain stays resident in one block: trajectory, dH, Metropolis and theta
- *   update separated by block barriers); this flag forces one launch per
- *   kernel per sweep instead.  Results are identical either way.
+ * RSV_FLAG_RESIDENT: rsv_hmc_sweep runs every sweep of a call in a single
+ *   launch (when the tile shape has one or four wavefronts and no chain has
+ *   more than 64 tiles): whole chains are packed into bins, one block per
+ *   bin, which integrates its tiles, then runs one finalize (dH total,
+ *   Metropolis test, theta update) per chain on one of its wavefronts, with
+ *   a block barrier between, for every sweep.  Without the flag each sweep
+ *   is one launch of the trajectory kernel and one of the finalize kernel,
+ *   which measures faster on MI355X at every problem size tried (the fused
+ *   kernel needs more registers and its blocks wait for their serial
+ *   finalize).  Results are identical either way, bit for bit.
  * RSV_FLAG_LEVEL_MOVE: every theta update (rsv_hmc_sweep with update_theta,
  *   rsv_theta_update) first moves the whole state along h_t -> h_t + c,
  *   mu -> mu + c, xi -> xi - c (xi only with RSV_TERM_RV).  That direction
@@ -112,7 +117,7 @@ enum { RSV_TERM_RETURN = 1, RSV_TERM_RV = 2, RSV_TERMS_RSV = 3 };
  *   most one of RSV_FLAG_OMELYAN and RSV_FLAG_FOREST_RUTH (EINVAL if both).
  *   Off by default. */
 enum {
-    RSV_FLAG_NO_RESIDENT = 1,
+    RSV_FLAG_RESIDENT = 1,
     RSV_FLAG_LEVEL_MOVE = 2,
     RSV_FLAG_OMELYAN = 4,
     RSV_FLAG_FOREST_RUTH = 8
@@ -150,7 +155,9 @@ typedef struct {
     int32_t waves_per_tile;     /* wavefronts per tile (0 = default 4; compiled
                                    (S, NW): F64 S in {4, 8} x NW in {1, 2, 4,
                                    8}; F32 S = 8 x NW in {1, 2, 4, 8} and
-                                   S = 16 x NW in {1, 2, 4}).
+                                   S = 16 x NW in {1, 2, 4}).  Resident
+                                   sweeps (see RSV_FLAG_RESIDENT) run for
+                                   NW in {1, 4}.
                                    A tile spans 64 * waves_per_tile *
                                    sites_per_lane sites, of which all but a
                                    k+1 halo on each cut side are exact          */
@@ -176,11 +183,10 @@ typedef struct {
                             state precision (FP64 or FP32)                      */
     /* Moment accumulators for runs too long to store (batch means): after
      * sweep i of the call, h is added to h_batch_sum[(i / batch_len) * n_state
-     * + site] and h^2 to h_sq_sum[site] (FP64; the caller zeroes them).  When
-     * the sweeps run one launch per kernel (not every chain fits one tile, or
-     * RSV_FLAG_NO_RESIDENT) the states of a batch are summed in FP32 and the
-     * batch total is added to these arrays (relative error ~ batch_len *
-     * 6e-8); resident sweeps add every state in FP64. */
+     * + site] and h^2 to h_sq_sum[site] (FP64; the caller zeroes them).  The
+     * states of a batch are summed in FP32 in the workspace and the batch
+     * total is added to these arrays (relative error ~ batch_len * 6e-8;
+     * without h_batch_sum the squares are added every 64 sweeps). */
     double *h_batch_sum; /* device, ceil(n_sweeps / batch_len) * n_state, or NULL */
     double *h_sq_sum;    /* device, n_state, or NULL                            */
     int32_t batch_len;   /* sweeps per batch (>= 1 when h_batch_sum is set)    */
@@ -286,11 +292,13 @@ rsv_status rsv_hmc_check(rsv_ctx *c, int64_t *n_nonfinite);
 
 /* Kernel timing (measurement support).  rsv_hmc_profile allocates
  * max_records pairs of HIP events (0 frees them); while records remain, each
- * later trajectory (in rsv_hmc_trajectory or one sweep of rsv_hmc_sweep) is
- * bracketed by a pair recorded on the context's stream around the
- * trajectory kernels only.  rsv_hmc_kernel_time waits for the last record,
- * returns the summed milliseconds and the number of records, and starts a
- * new series of records. */
+ * later trajectory launch (in rsv_hmc_trajectory or one sweep of
+ * rsv_hmc_sweep) is bracketed by a pair recorded on the context's stream
+ * around the trajectory kernel only, and a resident launch (all sweeps of an
+ * rsv_hmc_sweep call) by one pair around it.  rsv_hmc_kernel_time waits for
+ * the last record, returns the summed milliseconds and the number of
+ * trajectories the records cover (a resident launch of n sweeps counts n),
+ * and starts a new series of records. */
 rsv_status rsv_hmc_profile(rsv_ctx *c, int32_t max_records);
 rsv_status rsv_hmc_kernel_time(rsv_ctx *c, double *total_ms, int64_t *n_records);
 

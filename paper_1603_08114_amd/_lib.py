@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "librsvhmc.so")
 RSV_OK, RSV_EINVAL, RSV_EDEVICE, RSV_ENOMEM, RSV_ESTATE, RSV_ENONFINITE = 0, -1, -2, -3, -4, -5
 RSV_F64, RSV_F32_MIXED = 0, 1
 RSV_TERM_RETURN, RSV_TERM_RV, RSV_TERMS_RSV = 1, 2, 3
-RSV_FLAG_NO_RESIDENT = 1
+RSV_FLAG_RESIDENT = 1
 RSV_FLAG_LEVEL_MOVE = 2
 RSV_FLAG_OMELYAN = 4
 RSV_FLAG_FOREST_RUTH = 8

@@ -6,6 +6,7 @@
 // rsv_resident.hip) on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -101,7 +102,7 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_kicks) {
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
            edge = 0, accept = 0, shift = 0, mass_inv = 0, mass_sqrt = 0, acc = 0, counters = 0,
-           total = 0;
+           bins = 0, bin_chains = 0, bin_tiles = 0, total = 0;
     int32_t max_tiles = 0;
 };
 
@@ -125,7 +126,7 @@ rsv_status check_problem(const rsv_problem* pb, int64_t* n_data, int64_t* n_stat
     if (pb->max_steps < 1) return fail(RSV_EINVAL, "max_steps must be >= 1");
     if (!(pb->dtau_jitter >= 0.0 && pb->dtau_jitter < 1.0))
         return fail(RSV_EINVAL, "dtau_jitter must be in [0, 1)");
-    if (pb->flags & ~(RSV_FLAG_NO_RESIDENT | RSV_FLAG_LEVEL_MOVE | RSV_FLAG_OMELYAN |
+    if (pb->flags & ~(RSV_FLAG_RESIDENT | RSV_FLAG_LEVEL_MOVE | RSV_FLAG_OMELYAN |
                       RSV_FLAG_FOREST_RUTH))
         return fail(RSV_EINVAL, "unknown flags 0x%x", pb->flags);
     if ((pb->flags & RSV_FLAG_OMELYAN) && (pb->flags & RSV_FLAG_FOREST_RUTH))
@@ -191,6 +192,9 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->mass_sqrt = take(n_data * sizeof(double));
     L->acc = take(2 * n_state * sizeof(float));
     L->counters = take(kNumCounters * sizeof(uint32_t));
+    L->bins = take(n_chains * sizeof(BinDesc));
+    L->bin_chains = take(n_chains * sizeof(int32_t));
+    L->bin_tiles = take(tiles * sizeof(int32_t));
     L->total = off;
     L->max_tiles = static_cast<int32_t>(tiles);
     return RSV_OK;
@@ -228,15 +232,20 @@ struct rsv_ctx {
     double* mass_sqrt = nullptr;  // per data site sqrt(m_t)
     float* acc_f = nullptr;       // per state entry: FP32 batch sum, then batch sum of squares
     uint32_t* counters = nullptr;
+    BinDesc* bins = nullptr;          // resident sweeps: bins of chains, one per block
+    int32_t* bin_chains = nullptr;
+    int32_t* bin_tiles = nullptr;
     // host mirrors of the current decomposition
     std::vector<rsv_leapfrog> lf;
     std::vector<TileDesc> h_tiles;
     std::vector<ChainDesc> h_chains;
     int32_t n_body = 0, n_edge = 0;
     int32_t max_tiles_per_chain = 0;
-    bool single_tile = false;  // every chain is one tile
-    // kernel timing: event pairs around each trajectory-kernel launch
+    int32_t n_bins = 0;        // bins of the resident kernel (0: not available)
+    // kernel timing: event pairs around each trajectory-kernel launch (a
+    // resident launch is one pair covering all its sweeps)
     std::vector<hipEvent_t> ev_start, ev_stop;
+    std::vector<int64_t> ev_trajectories;  // trajectories each recorded pair covers
     size_t ev_used = 0;
 
     ~rsv_ctx() {
@@ -277,6 +286,65 @@ rsv_status usable(const rsv_ctx* c) {
 namespace {
 
 bool level_moves(const rsv_ctx* c) { return (c->pb.flags & RSV_FLAG_LEVEL_MOVE) != 0; }
+
+// Packs whole chains into bins for the resident kernel: a block integrates
+// its bin's tiles in rounds of kTPB tiles (four single-wavefront tiles, or
+// one tile of four wavefronts), so a bin holds up to kTPB * rounds tiles,
+// with rounds just enough for the longest chain.  Chains are placed largest
+// first into the bin with the least room that still fits them (best fit
+// decreasing); bins with more tiles come first.
+constexpr int kBinMaxChainTiles = 64;  // longer chains run one launch per kernel
+
+void pack_bins(const std::vector<ChainDesc>& chains, int tiles_per_round,
+               std::vector<BinDesc>& bins, std::vector<int32_t>& bin_chains,
+               std::vector<int32_t>& bin_tiles) {
+    struct Item { int32_t chain, tiles; };
+    std::vector<Item> items;
+    int32_t max_tiles = 1;
+    for (int32_t ch = 0; ch < static_cast<int32_t>(chains.size()); ++ch) {
+        const ChainDesc& d = chains[ch];
+        items.push_back(Item{ch, d.tile_count + (d.edge_tile >= 0 ? 1 : 0)});
+        max_tiles = std::max(max_tiles, items.back().tiles);
+    }
+    const int32_t cap = tiles_per_round * ((max_tiles + tiles_per_round - 1) / tiles_per_round);
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& b) { return a.tiles > b.tiles; });
+    std::vector<std::vector<int32_t>> members;   // chains of each bin
+    std::vector<int32_t> used;
+    std::vector<std::vector<int32_t>> by_room(cap + 1);  // open bins by free tiles
+    for (const Item& it : items) {
+        int32_t b = -1;
+        for (int room = it.tiles; room <= cap && b < 0; ++room) {
+            if (!by_room[room].empty()) {
+                b = by_room[room].front();
+                by_room[room].erase(by_room[room].begin());
+            }
+        }
+        if (b < 0) {
+            b = static_cast<int32_t>(members.size());
+            members.emplace_back();
+            used.push_back(0);
+        }
+        members[b].push_back(it.chain);
+        used[b] += it.tiles;
+        if (used[b] < cap) by_room[cap - used[b]].push_back(b);
+    }
+    std::vector<int32_t> order(members.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int32_t>(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return used[a] > used[b]; });
+    for (int32_t b : order) {
+        BinDesc d{static_cast<int32_t>(bin_chains.size()), static_cast<int32_t>(members[b].size()),
+                  static_cast<int32_t>(bin_tiles.size()), used[b]};
+        for (int32_t ch : members[b]) {
+            bin_chains.push_back(ch);
+            const ChainDesc& cd = chains[ch];
+            for (int32_t t = 0; t < cd.tile_count; ++t) bin_tiles.push_back(cd.tile_begin + t);
+            if (cd.edge_tile >= 0) bin_tiles.push_back(cd.edge_tile);
+        }
+        bins.push_back(d);
+    }
+}
 
 rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
     for (int s = 0; s < c->pb.n_series; ++s) {
@@ -319,13 +387,16 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
         chains[ch].tile_begin += n_edge;
     }
     c->max_tiles_per_chain = 0;
-    c->single_tile = true;
-    for (const ChainDesc& d : chains) {
+    for (const ChainDesc& d : chains)
         c->max_tiles_per_chain = std::max(c->max_tiles_per_chain, d.tile_count + 1);
-        c->single_tile = c->single_tile && (d.tile_count + (d.edge_tile >= 0 ? 1 : 0) == 1);
-    }
     c->n_body = static_cast<int32_t>(body.size());
     c->n_edge = static_cast<int32_t>(edges.size());
+    c->n_bins = 0;
+    std::vector<BinDesc> bins;
+    std::vector<int32_t> bin_chains, bin_tiles;
+    if (c->max_tiles_per_chain - 1 <= kBinMaxChainTiles &&
+        bin_shape_available(c->pb.precision, c->S, c->NW))
+        pack_bins(chains, c->NW == 1 ? 4 : 1, bins, bin_chains, bin_tiles);
     c->h_tiles = edges;
     c->h_tiles.insert(c->h_tiles.end(), body.begin(), body.end());
     c->h_chains = chains;
@@ -333,7 +404,17 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
                            hipMemcpyHostToDevice, c->stream));
     RSV_HIP(hipMemcpyAsync(c->chains, c->h_chains.data(), c->h_chains.size() * sizeof(ChainDesc),
                            hipMemcpyHostToDevice, c->stream));
+    if (!bins.empty()) {
+        RSV_HIP(hipMemcpyAsync(c->bins, bins.data(), bins.size() * sizeof(BinDesc),
+                               hipMemcpyHostToDevice, c->stream));
+        RSV_HIP(hipMemcpyAsync(c->bin_chains, bin_chains.data(),
+                               bin_chains.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               c->stream));
+        RSV_HIP(hipMemcpyAsync(c->bin_tiles, bin_tiles.data(), bin_tiles.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, c->stream));
+    }
     RSV_HIP(hipStreamSynchronize(c->stream));
+    c->n_bins = static_cast<int32_t>(bins.size());
     c->lf.assign(lf, lf + c->pb.n_series);
     return RSV_OK;
 }
@@ -412,7 +493,10 @@ rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, float* 
     a.tile_first = 0;
     a.n_list = c->n_body + c->n_edge;
     RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, c->NW, mass, &a));
-    if (timed) RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used++], c->stream));
+    if (timed) {
+        RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used], c->stream));
+        c->ev_trajectories[c->ev_used++] = 1;
+    }
     return RSV_OK;
 }
 
@@ -465,23 +549,42 @@ rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const do
     return RSV_OK;
 }
 
+// Every sweep of the call in one launch of the resident kernel.
 template <typename R>
-rsv_status run_resident(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps, int update_theta,
-                        const rsv_trace* trace) {
-    ResidentArgs<R> ra;
-    ra.traj = traj_args<R>(c, first_sweep, nullptr);
-    ra.fin = finalize_args(c, first_sweep, 1, update_theta);
-    ra.n_sweeps = n_sweeps;
-    ra.batch_len = (trace && trace->h_batch_sum) ? trace->batch_len : 1;
-    ra.first_sweep = first_sweep;
-    ra.n_state = c->n_state;
-    ra.dh_trace = trace ? trace->delta_h : nullptr;
-    ra.acc_trace = trace ? trace->accepted : nullptr;
-    ra.theta_trace = trace ? trace->theta : nullptr;
-    ra.h_trace = trace ? static_cast<R*>(trace->h) : nullptr;
-    ra.batch_sum = trace ? trace->h_batch_sum : nullptr;
-    ra.sq_sum = trace ? trace->h_sq_sum : nullptr;
-    RSV_HIP(launch_resident(c->stream, c->pb.precision, c->S, c->log_mass != nullptr, &ra));
+rsv_status run_bin(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps, int update_theta,
+                   const rsv_trace* trace) {
+    BinArgs<R> ba;
+    ba.traj = traj_args<R>(c, first_sweep, nullptr);
+    ba.fin = finalize_args(c, first_sweep, 1, update_theta);
+    ba.bins = c->bins;
+    ba.bin_chains = c->bin_chains;
+    ba.bin_tiles = c->bin_tiles;
+    ba.n_bins = c->n_bins;
+    ba.n_sweeps = n_sweeps;
+    ba.reserved = 0;
+    ba.first_sweep = first_sweep;
+    ba.n_state = c->n_state;
+    ba.dh_trace = trace ? trace->delta_h : nullptr;
+    ba.acc_trace = trace ? trace->accepted : nullptr;
+    ba.theta_trace = trace ? trace->theta : nullptr;
+    ba.h_trace = trace ? static_cast<R*>(trace->h) : nullptr;
+    const bool acc = trace && (trace->h_batch_sum || trace->h_sq_sum);
+    // batch sums as on the per-kernel path: the states of a batch summed in
+    // FP32 and added to the caller's FP64 arrays at the end of the batch
+    // (squares alone: every 64 sweeps)
+    ba.batch_len = (trace && trace->h_batch_sum) ? trace->batch_len : 64;
+    ba.acc_sum = acc ? c->acc_f : nullptr;
+    ba.acc_sq = acc ? c->acc_f + c->n_state : nullptr;
+    ba.batch_sum = trace ? trace->h_batch_sum : nullptr;
+    ba.sq_sum = trace ? trace->h_sq_sum : nullptr;
+    if (acc) RSV_HIP(launch_flush(c->stream, c->n_state, ba.acc_sum, ba.acc_sq, nullptr, nullptr));
+    const bool timed = c->ev_used < c->ev_start.size();
+    if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
+    RSV_HIP(launch_bin(c->stream, c->pb.precision, c->S, c->NW, c->log_mass != nullptr, &ba));
+    if (timed) {
+        RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used], c->stream));
+        c->ev_trajectories[c->ev_used++] = n_sweeps;
+    }
     return RSV_OK;
 }
 
@@ -558,6 +661,9 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->mass_sqrt = reinterpret_cast<double*>(c->ws + L.mass_sqrt);
     c->acc_f = reinterpret_cast<float*>(c->ws + L.acc);
     c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
+    c->bins = reinterpret_cast<BinDesc*>(c->ws + L.bins);
+    c->bin_chains = reinterpret_cast<int32_t*>(c->ws + L.bin_chains);
+    c->bin_tiles = reinterpret_cast<int32_t*>(c->ws + L.bin_tiles);
 
     auto bail = [&](rsv_status s) {
         delete c;
@@ -693,12 +799,10 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
     if (st != RSV_OK) return st;
     st = ensure_tiles(c, lf);
     if (st != RSV_OK) return st;
-    const bool timing = c->ev_used < c->ev_start.size();
-    if (n_sweeps > 0 && c->single_tile && c->NW == 4 && !timing &&
-        !(c->pb.flags & RSV_FLAG_NO_RESIDENT)) {
+    if (n_sweeps > 0 && c->n_bins > 0 && (c->pb.flags & RSV_FLAG_RESIDENT)) {
         st = c->pb.precision == RSV_F64
-                 ? run_resident<double>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace)
-                 : run_resident<float>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace);
+                 ? run_bin<double>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace)
+                 : run_bin<float>(c, first_sweep, n_sweeps, update_theta ? 1 : 0, trace);
         return st != RSV_OK ? st : settle(c);
     }
     const size_t elem = c->pb.precision == RSV_F64 ? sizeof(double) : sizeof(float);
@@ -777,20 +881,23 @@ rsv_status rsv_hmc_profile(rsv_ctx* c, int32_t max_records) {
         c->ev_start.push_back(a);
         c->ev_stop.push_back(b);
     }
+    c->ev_trajectories.assign(max_records, 0);
     return RSV_OK;
 }
 
 rsv_status rsv_hmc_kernel_time(rsv_ctx* c, double* total_ms, int64_t* n_records) {
     if (rsv_status u = usable(c); u != RSV_OK) return u;
     double sum = 0.0;
+    int64_t n = 0;
     if (c->ev_used > 0) RSV_HIP(hipEventSynchronize(c->ev_stop[c->ev_used - 1]));
     for (size_t i = 0; i < c->ev_used; ++i) {
         float ms = 0.f;
         RSV_HIP(hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]));
         sum += ms;
+        n += c->ev_trajectories[i];
     }
     if (total_ms) *total_ms = sum;
-    if (n_records) *n_records = static_cast<int64_t>(c->ev_used);
+    if (n_records) *n_records = n;
     c->ev_used = 0;
     return RSV_OK;
 }

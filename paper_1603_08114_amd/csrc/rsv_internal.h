@@ -108,19 +108,34 @@ struct FinalizeArgs {
 // Record the message returned by rsv_last_error() and return `code`.
 rsv_status set_error(rsv_status code, const char* where, const char* what);
 
+// Resident sweeps (rsv_bin.h): whole chains packed into bins, one per block.
+struct BinDesc {
+    int32_t chain_first;  // its chains are bin_chains[chain_first, + chain_count)
+    int32_t chain_count;
+    int32_t tile_first;   // their tiles are bin_tiles[tile_first, + tile_count)
+    int32_t tile_count;
+};
+
 template <typename R>
-struct ResidentArgs {
-    TrajArgs<R> traj;          // sweep field ignored (first_sweep + i)
-    FinalizeArgs fin;          // sweep and per-sweep outputs ignored (set per sweep)
+struct BinArgs {
+    TrajArgs<R> traj;          // sweep and acc_sum/acc_sq set per sweep
+    FinalizeArgs fin;          // sweep and per-sweep outputs set per sweep
+    const BinDesc* bins;
+    const int32_t* bin_chains;  // chain indices
+    const int32_t* bin_tiles;   // tile indices
+    int32_t n_bins;
     int32_t n_sweeps;
-    int32_t batch_len;
+    int32_t batch_len;         // sweeps per batch of the FP32 batch sums
+    int32_t reserved;
     uint64_t first_sweep;
     int64_t n_state;
     double* dh_trace;          // n_sweeps * n_chains or nullptr
     int32_t* acc_trace;
     rsv_theta* theta_trace;
     R* h_trace;                // n_sweeps * n_state or nullptr
-    double* batch_sum;         // accumulators (see rsv_trace) or nullptr
+    float* acc_sum;            // FP32 sums of the current batch (or nullptr)
+    float* acc_sq;
+    double* batch_sum;         // the caller's accumulators (see rsv_trace) or nullptr
     double* sq_sum;
 };
 
@@ -139,8 +154,11 @@ hipError_t launch_traj_f32_mass(hipStream_t st, int S, int NW, const TrajArgs<fl
 bool traj_shape_available(int precision, int S, int NW);
 void traj_default_shape(int precision, int* S, int* NW);
 hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_tiles_per_chain);
-// All n sweeps of chains that each fit one tile of four wavefronts, in one launch.
-hipError_t launch_resident(hipStream_t st, int precision, int S, bool mass, const void* args);
+// All n sweeps of chains that each fit one tile, packed into bins, in one launch.
+hipError_t launch_bin(hipStream_t st, int precision, int S, int NW, bool mass, const void* args);
+hipError_t launch_bin_f64(hipStream_t st, int S, int NW, bool mass, const BinArgs<double>& a);
+hipError_t launch_bin_f32(hipStream_t st, int S, int NW, bool mass, const BinArgs<float>& a);
+bool bin_shape_available(int precision, int S, int NW);
 // Copy every chain's current state (selected by state_sel) into h_dst.
 hipError_t launch_gather_state(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
                                int32_t max_T, const int32_t* state_sel, const void* h_a,

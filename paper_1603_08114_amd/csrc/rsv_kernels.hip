@@ -161,6 +161,18 @@ bool traj_shape_available(int precision, int S, int NW) {
     if (precision == RSV_F64) return nw && (S == 4 || S == 8);
     return (S == 8 && nw) || (S == 16 && (NW == 1 || NW == 2 || NW == 4));
 }
+// Shapes of the resident kernel (rsv_bin.h): single-wavefront tiles and tiles
+// of four wavefronts.
+bool bin_shape_available(int precision, int S, int NW) {
+    if (precision == RSV_F64) return (S == 4 || S == 8) && (NW == 1 || NW == 4);
+    return (S == 8 || S == 16) && (NW == 1 || NW == 4);
+}
+
+hipError_t launch_bin(hipStream_t st, int precision, int S, int NW, bool mass, const void* args) {
+    if (precision == RSV_F64)
+        return launch_bin_f64(st, S, NW, mass, *static_cast<const BinArgs<double>*>(args));
+    return launch_bin_f32(st, S, NW, mass, *static_cast<const BinArgs<float>*>(args));
+}
 void traj_default_shape(int precision, int* S, int* NW) {
     // fastest measured on a long series: FP64 (4, 4) (fewer registers, five
     // waves per SIMD), FP32 (8, 4)

@@ -62,6 +62,80 @@ __device__ inline double step_size(uint64_t seed, uint64_t sweep, uint64_t chain
 }
 
 // ---------------------------------------------------------------------------
+// Per-site arithmetic shared by the trajectory kernel and the resident
+// kernel (so that both produce bitwise the same results).
+// ---------------------------------------------------------------------------
+
+// One site of a momentum step (kick) p += dk g(h) of eqs. (6)-(8): with the
+// per-site constants dc = -dk (c_base - r/sigma_u^2) and ds = dk y^2 / 2 and
+// the per-chain mda = -dk alpha, db = dk beta, the force term is
+// dc + mda h + db (h_l + h_r) + ds e^{-h}.
+template <typename R, bool RET>
+__device__ __forceinline__ R kick_site(R p, R dc, R ds, R mda, R db, R h, R hl, R hr) {
+    R acc = p + dc;
+    acc += mda * h;
+    acc += db * (hl + hr);
+    if constexpr (RET) acc += ds * exp_neg<R>(h);
+    return acc;
+}
+
+// A kick with the constants of a step of dt, scaled by the kick's factor kf
+// (Forest-Ruth's unequal kicks).
+template <typename R, bool RET>
+__device__ __forceinline__ R kick_site_scaled(R p, R kf, R dc, R ds, R mda, R db, R h, R hl,
+                                              R hr) {
+    R acc = dc + mda * h;
+    acc += db * (hl + hr);
+    if constexpr (RET) acc += ds * exp_neg<R>(h);
+    return p + kf * acc;
+}
+
+// Per-lane sums of the dH pass: dH, the statistics {B, B2, BB, D1, D2} of
+// h' (s1) and of h (s0), and S = sum y^2 e^{-h} of h' and h.
+struct DhSums {
+    double dH, s1[5], s0[5], sy1, sy0;
+};
+
+// Adds exact site t to the sums: the per-site difference of H(h', p') -
+// H(h, p) (kinetic term, y and ln RV terms, the bond to site t+1 when
+// has_next, the stationary prior of site 0 when first) and the site's
+// statistics.  h1 = h'_t, h0 = h_t, pj = p'_t, im = 1/m_t, yy = y_t^2,
+// rr = ln RV_t, h1n / h0n the next site's values.  Returns h1 - mu, h0 - mu.
+template <bool RET>
+__device__ __forceinline__ void dh_site(DhSums& D, double h1, double h0, double pj, double im,
+                                        double yy, double rr, bool rv, bool has_next, double h1n,
+                                        double h0n, bool first, double mu, double phi, double xi,
+                                        double inv_se, double inv_su, double& a1, double& a0) {
+    double d = 0.5 * pj * pj * im;
+    if (RET) {
+        const double ye0 = yy * exp_fast(-h0);
+        const double x10 = exp_fast(h0 - h1);  // e^{-h1} / e^{-h0}
+        d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
+        D.sy1 += ye0 * x10;
+        D.sy0 += ye0;
+    }
+    if (rv) {
+        const double c = rr - xi;
+        const double e1 = c - h1, e0 = c - h0;
+        d += (e1 - e0) * (e1 + e0) * (0.5 * inv_su);
+    }
+    a1 = h1 - mu;
+    a0 = h0 - mu;
+    if (has_next) {
+        const double d1 = (h1n - mu) - phi * a1;
+        const double d0 = (h0n - mu) - phi * a0;
+        d += (d1 - d0) * (d1 + d0) * (0.5 * inv_se);
+        D.s1[2] += a1 * (h1n - mu);
+        D.s0[2] += a0 * (h0n - mu);
+    }
+    if (first) d += (1.0 - phi * phi) * (a1 - a0) * (a1 + a0) * (0.5 * inv_se);
+    D.dH += d;
+    const double e1 = rr - h1 - xi, e0 = rr - h0 - xi;
+    D.s1[0] += a1; D.s1[1] += a1 * a1; D.s1[3] += e1; D.s1[4] += e1 * e1;
+    D.s0[0] += a0; D.s0[1] += a0 * a0; D.s0[3] += e0; D.s0[4] += e0 * e0;
+}
+
+// ---------------------------------------------------------------------------
 // Trajectory kernel: momentum refresh, k leapfrog steps, per-site dH terms and
 // sufficient statistics of h' and h, for one tile per group of NW wavefronts.
 // Lane g = 64*wave + lane of a tile holds sites [la + g*S, la + (g+1)*S).
@@ -265,18 +339,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             if constexpr (EDGE) {
                 if (j < S - 1 && t0 + j == T - 1) hr = ghost_neighbour(h[j], s_mu, s_phi);
             }
-            if constexpr (scaled) {
-                R acc = dc[j] + s_mda * h[j];
-                acc += s_db * (hl + hr);
-                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
-                p[j] += kf * acc;
-            } else {
-                R acc = p[j] + dc[j];
-                acc += s_mda * h[j];
-                acc += s_db * (hl + hr);
-                if constexpr (RET) acc += ds[j] * exp_neg<R>(h[j]);
-                p[j] = acc;
-            }
+            if constexpr (scaled)
+                p[j] = kick_site_scaled<R, RET>(p[j], kf, dc[j], ds[j], s_mda, s_db, h[j], hl, hr);
+            else
+                p[j] = kick_site<R, RET>(p[j], dc[j], ds[j], s_mda, s_db, h[j], hl, hr);
         }
     };
     using Plain = std::false_type;
@@ -405,44 +471,21 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     // 1/m_t is read again here rather than kept live across the leapfrog loop
     const double* minv_again = minv;
     if constexpr (MASS) asm volatile("" : "+v"(minv_again));
-    double dH = -kin0;
-    double s1[5] = {0, 0, 0, 0, 0}, s0[5] = {0, 0, 0, 0, 0};
-    double sy1 = 0.0, sy0 = 0.0;  // sum y^2 e^{-h} of h' and h
+    DhSums D = {-kin0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, 0.0, 0.0};
     double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         if (t < td.a || t >= td.b) continue;
-        const double h1 = static_cast<double>(h[j]);
-        const double h0 = h0d[j];
-        const double pj = static_cast<double>(p[j]);
         const double im = MASS ? minv_again[t] : 1.0;
         const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
-        double d = 0.5 * pj * pj * im;
-        if (RET) {
-            const double ye0 = (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) * exp_fast(-h0);
-            const double x10 = exp_fast(h0 - h1);  // e^{-h1} / e^{-h0}
-            d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
-            sy1 += ye0 * x10;
-            sy0 += ye0;
-        }
-        if (rv) {
-            const double c = rr - xi;
-            const double e1 = c - h1, e0 = c - h0;
-            d += (e1 - e0) * (e1 + e0) * (0.5 * inv_su);
-        }
-        const double a1 = h1 - mu, a0 = h0 - mu;
-        if (t + 1 < T) {
-            const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + 1]);
-            const double h0n = (j == S - 1) ? h0_up : h0d[j + 1];
-            const double d1 = (h1n - mu) - phi * a1;
-            const double d0 = (h0n - mu) - phi * a0;
-            d += (d1 - d0) * (d1 + d0) * (0.5 * inv_se);
-            s1[2] += a1 * (h1n - mu);
-            s0[2] += a0 * (h0n - mu);
-        }
+        const double yy = RET ? (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) : 0.0;
+        const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + (j < S - 1)]);
+        const double h0n = (j == S - 1) ? h0_up : h0d[j + (j < S - 1)];
+        double a1, a0;
+        dh_site<RET>(D, static_cast<double>(h[j]), h0d[j], static_cast<double>(p[j]), im, yy, rr,
+                     rv, t + 1 < T, h1n, h0n, t == 0, mu, phi, xi, inv_se, inv_su, a1, a0);
         if (t == 0) {
-            d += (1.0 - phi * phi) * (a1 - a0) * (a1 + a0) * (0.5 * inv_se);
             edge[0] = a1;
             edge[2] = a0;
         }
@@ -450,21 +493,17 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             edge[1] = a1;
             edge[3] = a0;
         }
-        dH += d;
-        const double e1 = rr - h1 - xi, e0 = rr - h0 - xi;
-        s1[0] += a1; s1[1] += a1 * a1; s1[3] += e1; s1[4] += e1 * e1;
-        s0[0] += a0; s0[1] += a0 * a0; s0[3] += e0; s0[4] += e0 * e0;
         hp[t] = h[j];
     }
 
     double red[kNQ];
-    red[kPartDH] = wave_sum(dH);
-    red[kPartSyProp] = wave_sum(sy1);
-    red[kPartSyCur] = wave_sum(sy0);
+    red[kPartDH] = wave_sum(D.dH);
+    red[kPartSyProp] = wave_sum(D.sy1);
+    red[kPartSyCur] = wave_sum(D.sy0);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        red[kPartProp + q] = wave_sum(s1[q]);
-        red[kPartCur + q] = wave_sum(s0[q]);
+        red[kPartProp + q] = wave_sum(D.s1[q]);
+        red[kPartCur + q] = wave_sum(D.s0[q]);
     }
     if constexpr (NW > 1) {
         if (lane == 0) {
@@ -862,58 +901,82 @@ __device__ Decision finalize_decide(const FinalizeArgs& A, const int c, const in
     return Decision{use_prop, shift};
 }
 
-// Everything the finalize does for chain c, by the NT threads of a block
-// (shared scratch passed in); returns in every thread.
+// Synchronises the lanes of one wavefront through LDS.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Everything the finalize does for chain c, by NT threads (tid = 0..NT-1;
+// NT = 64: one wavefront, which may be one of several in its block) with
+// shared scratch passed in; returns in every thread.
 template <int NT>
 __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[NT / kWave][kNQ],
-                               ThetaDraws& draws) {
+                               ThetaDraws& draws, const int tid) {
     constexpr int NW = NT / kWave;
     constexpr int NQ = kNQ;
-    const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
     const ChainDesc cd = A.chains[c];
 
     finalize_draws(A, c, cd.T, tid, NT, draws);
 
-    Comp acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
     const double* chain_parts = A.partials + static_cast<int64_t>(cd.tile_begin) * kPart;
-    int i = tid;
-    if constexpr (NT >= 256) {
-        // chains of thousands of tiles: the partials of four tiles are loaded
-        // before any is added, so their memory latencies overlap (same order
-        // of additions as one tile at a time)
-        for (; i + 3 * NT < cd.tile_count; i += 4 * NT) {
-            double v[4][NQ];
+    if constexpr (NT == kWave) {
+        // one wavefront: one quantity at a time (the same additions per
+        // quantity as below, with one accumulator live instead of NQ)
+        for (int q = 0; q < NQ; ++q) {
+            Comp acc{0.0, 0.0};
+            for (int i = tid; i < cd.tile_count; i += NT)
+                comp_add(acc, chain_parts[static_cast<int64_t>(i) * kPart + q]);
+            if (tid == 0 && cd.edge_tile >= 0)
+                comp_add(acc, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + q]);
+            const Comp r = wave_comp_sum(acc);
+            if (lane == 0) part[0][q] = r;
+        }
+    } else {
+        Comp acc[NQ];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+        for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
+        int i = tid;
+        if constexpr (NT >= 256) {
+            // chains of thousands of tiles: the partials of four tiles are
+            // loaded before any is added, so their memory latencies overlap
+            // (same order of additions as one tile at a time)
+            for (; i + 3 * NT < cd.tile_count; i += 4 * NT) {
+                double v[4][NQ];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    v[u][q] = chain_parts[static_cast<int64_t>(i + u * NT) * kPart + q];
+                for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+                    for (int q = 0; q < NQ; ++q)
+                        v[u][q] = chain_parts[static_cast<int64_t>(i + u * NT) * kPart + q];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) comp_add(acc[q], v[u][q]);
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) comp_add(acc[q], v[u][q]);
+            }
+        }
+        for (; i < cd.tile_count; i += NT) {
+            const double* pp = chain_parts + static_cast<int64_t>(i) * kPart;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
+        }
+        if (tid == 0 && cd.edge_tile >= 0) {
+            const double* pp = A.partials + static_cast<int64_t>(cd.edge_tile) * kPart;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const Comp r = wave_comp_sum(acc[q]);
+            if (lane == 0) part[wv][q] = r;
         }
     }
-    for (; i < cd.tile_count; i += NT) {
-        const double* pp = chain_parts + static_cast<int64_t>(i) * kPart;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
-    }
-    if (tid == 0 && cd.edge_tile >= 0) {
-        const double* pp = A.partials + static_cast<int64_t>(cd.edge_tile) * kPart;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const Comp r = wave_comp_sum(acc[q]);
-        if (lane == 0) part[wv][q] = r;
-    }
-    __syncthreads();
+    if constexpr (NT == kWave)
+        wave_sync();
+    else
+        __syncthreads();
     if (tid != 0) return;
     double tot[NQ];
 #pragma unroll
@@ -934,64 +997,9 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
     __shared__ Comp part[NT / kWave][kNQ];
     __shared__ ThetaDraws draws;
-    finalize_chain<NT>(A, blockIdx.x, part, draws);
+    finalize_chain<NT>(A, blockIdx.x, part, draws, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Resident sweeps: chains that fit one tile of four wavefronts run all n
-// sweeps (trajectory, dH, Metropolis, theta update, traces) in one launch,
-// one block per chain; the phases are separated by block barriers.
-// ---------------------------------------------------------------------------
-template <typename R, int S, bool MASS, bool RET>
-__global__ __launch_bounds__(256) void k_resident(ResidentArgs<R> RA) {
-    using St = Stage<R, S, 4, 1>;
-    __shared__ TileShared<R, 4> sh;
-    __shared__ double stage[St::n];
-    __shared__ Comp part[4][kNQ];
-    __shared__ ThetaDraws draws;
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const ChainDesc cd = RA.traj.chains[c];
-    const bool edge = cd.edge_tile >= 0;
-    const int tile_id = edge ? cd.edge_tile : cd.tile_begin;
-    const int n_chains = RA.fin.n_chains;
-    for (int i = 0; i < RA.n_sweeps; ++i) {
-        TrajArgs<R> A = RA.traj;
-        A.sweep = RA.first_sweep + static_cast<uint64_t>(i);
-        if (edge)
-            traj_tile<R, S, 4, MASS, true, RET, St::on>(A, sh, tile_id, wv, lane, stage);
-        else
-            traj_tile<R, S, 4, MASS, false, RET, St::on>(A, sh, tile_id, wv, lane, stage);
-        __syncthreads();
-        FinalizeArgs F = RA.fin;
-        F.sweep = A.sweep;
-        const int64_t ofs = static_cast<int64_t>(i) * n_chains;
-        F.delta_h_out = RA.dh_trace ? RA.dh_trace + ofs : nullptr;
-        F.accepted_out = RA.acc_trace ? RA.acc_trace + ofs : nullptr;
-        F.theta_trace = RA.theta_trace ? RA.theta_trace + ofs : nullptr;
-        finalize_chain<256>(F, c, part, draws);
-        __syncthreads();
-        if (RA.h_trace || RA.batch_sum || RA.sq_sum) {
-            const R* src = (RA.traj.state_sel[c] ? RA.traj.h_b : RA.traj.h_a) + cd.h_off;
-            const double sft = RA.fin.shift ? RA.fin.shift[c] : 0.0;
-            R* ht = RA.h_trace ? RA.h_trace + static_cast<int64_t>(i) * RA.n_state + cd.h_off
-                               : nullptr;
-            double* bs = RA.batch_sum
-                             ? RA.batch_sum + static_cast<int64_t>(i / RA.batch_len) * RA.n_state + cd.h_off
-                             : nullptr;
-            double* sq = RA.sq_sum ? RA.sq_sum + cd.h_off : nullptr;
-            for (int t = threadIdx.x; t < cd.T; t += blockDim.x) {
-                const R v = state_at(src, t, sft);
-                if (ht) ht[t] = v;
-                const double vd = static_cast<double>(v);
-                if (bs) bs[t] += vd;
-                if (sq) sq[t] = __builtin_fma(vd, vd, sq[t]);
-            }
-            __syncthreads();
-        }
-    }
-}
 }  // namespace
 
 }  // namespace rsv

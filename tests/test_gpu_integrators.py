@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1603_08114_amd import api  # noqa: E402
 from paper_1603_08114_amd._lib import (RSV_F32_MIXED, RSV_FLAG_FOREST_RUTH,  # noqa: E402
-                                       RSV_FLAG_LEVEL_MOVE, RSV_FLAG_NO_RESIDENT,
+                                       RSV_FLAG_LEVEL_MOVE, RSV_FLAG_RESIDENT,
                                        RSV_FLAG_OMELYAN)
 from _parity import sweeps_with_resync  # noqa: E402
 from test_gpu_parity import (NEAR_TIE, TH, _resync_builder, chain_slices,  # noqa: E402
@@ -154,11 +154,15 @@ def test_sweeps_match_oracle(flags, j, name):
     assert np.mean([r["accepted"].mean() for r in refs]) > 0.5
 
 
+@pytest.mark.parametrize("waves", [4, 1])
 @pytest.mark.parametrize("precision", [0, RSV_F32_MIXED])
 @pytest.mark.parametrize("name", list(INTEGRATORS))
-def test_resident_sweeps_equal_per_kernel_sweeps(precision, name):
+def test_resident_sweeps_equal_per_kernel_sweeps(precision, name, waves):
     flag = INTEGRATORS[name][0]
     Ts, C, k, dt, n = [1000, 37, 2048, 1501], 3, 10, 0.08, 30
+    if waves == 1:  # chains of several single-wavefront tiles
+        Ts = [4096, 37, 2048, 1501] if precision == 0 else [8000, 37, 2048, 5001]
+    S = 8
     if name == "forest_ruth":  # stiff batch thetas (omega up to ~20) need a small dtau
         k, dt = 7, 0.05
     thetas = synth.draw_batch_thetas(len(Ts), 9)
@@ -166,15 +170,15 @@ def test_resident_sweeps_equal_per_kernel_sweeps(precision, name):
     h0 = state_from(hs, C, 0.02)
     th = [thetas[s] for s in range(len(Ts)) for _ in range(C)]
     outs = []
-    for path in (0, RSV_FLAG_NO_RESIDENT):
+    for path in (0, RSV_FLAG_RESIDENT):
         smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
                              chains_per_series=C, precision=precision, max_steps=k, seed=4,
                              flags=flag | RSV_FLAG_LEVEL_MOVE | path,
-                             dtau_jitter=0.3, sites_per_lane=8, waves_per_tile=4)
-        o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True)
+                             dtau_jitter=0.3, sites_per_lane=S, waves_per_tile=waves)
+        o = smp.sweep(10, n, (k, dt), update_theta=True, record_h=True, batch_len=6)
         o["state"] = smp.h.clone()
         outs.append(o)
-    for key in ("delta_h", "accepted", "theta", "h", "state"):
+    for key in ("delta_h", "accepted", "theta", "h", "state", "h_batch_sum", "h_sq_sum"):
         a, b = outs[0][key], outs[1][key]
         if a.is_floating_point():  # a diverged trajectory gives NaN on both paths
             assert torch.equal(a.isnan(), b.isnan()), key

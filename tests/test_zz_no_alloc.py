@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_1603_08114_amd import api  # noqa: E402
 from paper_1603_08114_amd._lib import (RSV_ENOMEM, RSV_ESTATE, RSV_F32_MIXED,  # noqa: E402
-                                       RSV_F64, RSV_FLAG_NO_RESIDENT)
+                                       RSV_F64, RSV_FLAG_RESIDENT)
 
 
 def _problem(Ts, C, seed):
@@ -48,7 +48,7 @@ def _assert_same(a, b):
         assert torch.equal(x, y), key
 
 
-@pytest.mark.parametrize("precision,flags", [(RSV_F64, 0), (RSV_F32_MIXED, RSV_FLAG_NO_RESIDENT)])
+@pytest.mark.parametrize("precision,flags", [(RSV_F64, 0), (RSV_F32_MIXED, RSV_FLAG_RESIDENT)])
 def test_static_workspace_matches_caller_workspace(precision, flags):
     k, dt, n = 12, 0.04, 25
     # first call: several tiles per chain (per-kernel path), two chains per series
