@@ -920,22 +920,46 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
     const int wv = tid / kWave;
     const ChainDesc cd = A.chains[c];
 
-    finalize_draws(A, c, cd.T, tid, NT, draws);
-
     const double* chain_parts = A.partials + static_cast<int64_t>(cd.tile_begin) * kPart;
     if constexpr (NT == kWave) {
-        // one wavefront: one quantity at a time (the same additions per
-        // quantity as below, with one accumulator live instead of NQ)
-        for (int q = 0; q < NQ; ++q) {
-            Comp acc{0.0, 0.0};
-            for (int i = tid; i < cd.tile_count; i += NT)
-                comp_add(acc, chain_parts[static_cast<int64_t>(i) * kPart + q]);
-            if (tid == 0 && cd.edge_tile >= 0)
-                comp_add(acc, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + q]);
-            const Comp r = wave_comp_sum(acc);
-            if (lane == 0) part[0][q] = r;
+        // one wavefront, chains of at most 64 body tiles: each lane's tile
+        // (and lane 0's edge tile) is loaded before the random draws, so the
+        // loads' latency overlaps with them; then one quantity at a time (the
+        // same additions as the general path below)
+        if (cd.tile_count <= NT) {
+            const bool has = tid < cd.tile_count;
+            const bool has_edge = tid == 0 && cd.edge_tile >= 0;
+            const double* pt = chain_parts + static_cast<int64_t>(has ? tid : 0) * kPart;
+            const double* pe = A.partials + static_cast<int64_t>(has_edge ? cd.edge_tile : 0) * kPart;
+            double v[NQ], ve[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                v[q] = has ? pt[q] : 0.0;
+                ve[q] = has_edge ? pe[q] : 0.0;
+            }
+            finalize_draws(A, c, cd.T, tid, NT, draws);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                Comp acc{0.0, 0.0};
+                if (has) comp_add(acc, v[q]);
+                if (has_edge) comp_add(acc, ve[q]);
+                const Comp r = wave_comp_sum(acc);
+                if (lane == 0) part[0][q] = r;
+            }
+        } else {
+            finalize_draws(A, c, cd.T, tid, NT, draws);
+            for (int q = 0; q < NQ; ++q) {
+                Comp acc{0.0, 0.0};
+                for (int i = tid; i < cd.tile_count; i += NT)
+                    comp_add(acc, chain_parts[static_cast<int64_t>(i) * kPart + q]);
+                if (tid == 0 && cd.edge_tile >= 0)
+                    comp_add(acc, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + q]);
+                const Comp r = wave_comp_sum(acc);
+                if (lane == 0) part[0][q] = r;
+            }
         }
     } else {
+        finalize_draws(A, c, cd.T, tid, NT, draws);
         Comp acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
