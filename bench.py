@@ -29,9 +29,15 @@ if ROOT not in sys.path:
 
 METRIC = "min-ESS/s and leapfrog site-updates/s; learned-mass FP32 vs plain FP64 HMC"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one instruction per
+# lane per clock (T lane-instructions/s); FMA-counted this is the FP64 vector
+# peak of 78.6 TFLOP/s, and the FP32 peak without packed FP32 (which this
+# build disables; 157.3 TFLOP/s needs it)
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS_UNPACKED = 78.6
 STREAM_BYTES = {"f64": 48, "f32": 24}   # read h,p,y^2,lnRV + write h,p per site-update
+HOST_CORES_MAX = 16                      # the host-core share of one GPU on the measuring box
 
 
 def parse():
@@ -56,6 +62,8 @@ def parse():
                          "0.5 for batched, mass and the precision study's chains)")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="long workload only: skip the single-series and batched min-ESS/s legs")
     ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "precision"],
                     default="long",
                     help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
@@ -161,17 +169,50 @@ def summarize_counters(fetch_csv, write_csv, calib_fetch_csv, calib_write_csv, k
     print(json.dumps(out, indent=1))
 
 
+def host_cpu():
+    """Host cores this process may use (capped at one GPU's share) and the CPU model."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return min(n, HOST_CORES_MAX), n, model
+
+
 def cpu_baseline(y, lr, h0, theta, k, dtau, n_sweeps, seed, T):
-    import numpy as np
+    """The oracle (serial C, FP64) on the host: one chain on one core, then
+    one independent chain per core on all cores (threads; the ctypes calls
+    release the GIL), each chain n_sweeps sweeps of the same series."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
+    y2 = y * y
     t0 = time.perf_counter()
-    oracle.run(h0, theta, y * y, lr, k, dtau, n_sweeps, seed=seed, update_theta=True)
-    dt = time.perf_counter() - t0
-    return {"value": T * k * n_sweeps / dt, "unit": "site-updates/s", "cores": 1,
+    oracle.run(h0, theta, y2, lr, k, dtau, n_sweeps, seed=seed, update_theta=True)
+    dt1 = time.perf_counter() - t0
+    cores, nproc, model = host_cpu()
+
+    def one(chain):
+        oracle.run(h0, theta, y2, lr, k, dtau, n_sweeps, seed=seed, chain=chain, update_theta=True)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, range(cores)))
+    dtn = time.perf_counter() - t0
+    return {"value": T * k * n_sweeps * cores / dtn, "unit": "site-updates/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{n_sweeps} sweeps (trajectory + theta update) of the same T={T} series, "
-                      f"k={k}, FP64, serial C",
-            "seconds": dt}
+            "sample": f"{cores} independent chains (one per core, threads) x {n_sweeps} sweeps "
+                      f"(trajectory + theta update) of the same T={T} series, k={k}, FP64, "
+                      "serial C per chain",
+            "seconds": dtn, "nproc": nproc, "cpu_model": model,
+            "single_core": {"value": T * k * n_sweeps / dt1, "cores": 1, "seconds": dt1}}
 
 
 def min_ess_from_traces(h_trace, theta_trace):
@@ -235,8 +276,9 @@ def small_chain(jit, level, with_oracle, integrator="leapfrog"):
                        jitter=jit, moves=oracle.MOVE_LEVEL if level else 0, integrator=iorc)
         dt = _t.perf_counter() - t0
         m_ref, _, _ = min_ess_from_traces(r["h_trace"][burn:], r["theta_trace"][burn:])
+        _, nproc, model = host_cpu()
         ref = {"value": m_ref / (dt * n / (burn + n)), "unit": "min-ESS/s", "cores": 1,
-               "kind": "oracle",
+               "kind": "oracle", "nproc": nproc, "cpu_model": model,
                "sample": "the whole run (500 + 5000 sweeps), serial C; time pro-rated to the "
                          "5000 measured sweeps",
                "site_updates_per_s": T * k * (burn + n) / dt, "seconds": dt, "min_ess": m_ref}
@@ -284,130 +326,173 @@ def jitter_of(args, default):
     return default if args.dtau_jitter < 0 else args.dtau_jitter
 
 
-def run_batched(args):
-    """512 series, T ~ U{500..8000}, per-series theta, 4 chains each, k = 30,
-    FP32-mixed leapfrog, step size jittered +-50%; per-series dtau adapted to
-    ~0.8 acceptance over 500 warm-up sweeps; 2000 measured sweeps with batch
-    means (50 batches of 40) accumulated on the device.  value = median over
-    series of min-ESS/s."""
-    import torch
+def batched_data(S_=512, C_=4):
+    """512 series, T ~ U{500..8000}, per-series theta (seed 3), C chains each
+    starting from the simulated path."""
     import synth
-    from paper_1603_08114_amd import api, diagnostics
-    from paper_1603_08114_amd._lib import RSV_F32_MIXED
-    S_, C_, k = 512, 4, 30
     data = synth.make_batch(S_, 500, 8000, seed=3)
     off = data["offsets"]
+    data["h0"] = np.concatenate([np.tile(data["h_true"][off[s]:off[s + 1]], C_)
+                                 for s in range(S_)])
+    data["theta0"] = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
+    data["C"] = C_
+    return data
+
+
+def batched_arm(data, k, jit, level, omelyan=False, shape=None, n=2000, bl=40,
+                precision=None):
+    """Warm-up with dtau adapted per series to ~0.8 acceptance (10 windows of 50
+    sweeps), then n measured sweeps with batch means accumulated on the
+    device; min over {h_t} and theta of the ESS of each series (its chains
+    summed), per second of the measured sweeps.  shape None = autotuned."""
+    import torch
+    from paper_1603_08114_amd import api, autotune, diagnostics
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN
+    precision = RSV_F32_MIXED if precision is None else precision
+    off, C_ = data["offsets"], data["C"]
     Ts = np.diff(off)
-    h0 = np.concatenate([np.tile(data["h_true"][off[s]:off[s + 1]], C_) for s in range(S_)])
-    thetas = [data["thetas"][s] for s in range(S_) for _ in range(C_)]
-    jit = jitter_of(args, 0.5)
-    level = level_of(args, True)
-    from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN
-    from paper_1603_08114_amd import autotune
-
-    def arm(omelyan):
-        """Warm-up, dtau adaptation and the measured sweeps of one integrator:
-        the leapfrog with k = 30, or Omelyan's scheme with k = 15 (the same 30
-        force evaluations per trajectory, twice the starting dtau)."""
-        k_ = k // 2 if omelyan else k
-        dtau = (2.0 if omelyan else 1.0) * 0.05 * (1000.0 / Ts) ** 0.25
-        kw = dict(chains_per_series=C_, precision=RSV_F32_MIXED, dtau_jitter=jit,
-                  flags=(RSV_FLAG_LEVEL_MOVE if level else 0)
-                  | (RSV_FLAG_OMELYAN if omelyan else 0))
-        S_t, NW_t, shape_table = autotune.best_shape(off, data["y"], data["log_rv"], h0, thetas,
-                                                     [(k_, d) for d in dtau], n_sweeps=4, **kw)
-        print(f"[batched] autotuned tile shape S={S_t} NW={NW_t}: {shape_table}", file=sys.stderr,
+    S_ = Ts.size
+    k_ = k // 2 if omelyan else k
+    dtau = (2.0 if omelyan else 1.0) * 0.05 * (1000.0 / Ts) ** 0.25
+    kw = dict(chains_per_series=C_, precision=precision, dtau_jitter=jit,
+              flags=(RSV_FLAG_LEVEL_MOVE if level else 0) | (RSV_FLAG_OMELYAN if omelyan else 0))
+    table = None
+    if shape is None:
+        S_t, NW_t, table = autotune.best_shape(off, data["y"], data["log_rv"], data["h0"],
+                                               data["theta0"], [(k_, d) for d in dtau],
+                                               n_sweeps=4, **kw)
+        print(f"[batched] autotuned tile shape S={S_t} NW={NW_t}: {table}", file=sys.stderr,
               flush=True)
-        smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, max_steps=k_, seed=3,
-                             sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
-        sweep = 0
-        for _ in range(10):  # 10 windows of 50 warm-up sweeps
-            out = smp.sweep(sweep, 50, [(k_, d) for d in dtau], update_theta=True,
-                            record=("delta_h",))
-            sweep += 50
-            dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
-            acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
-            dtau = dtau * np.exp(1.5 * (acc - 0.8))
-        lf = [(k_, d) for d in dtau]
-        smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
-        sweep += 1
-        torch.cuda.synchronize()
-        n, bl = 2000, 40
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(smp.stream)
-        out = smp.sweep(sweep, n, lf, update_theta=True, record=("theta", "accepted"), batch_len=bl)
-        ev1.record(smp.stream)
-        torch.cuda.synchronize()
-        elapsed = ev0.elapsed_time(ev1) / 1e3
-        bsum = out["h_batch_sum"].cpu().numpy() / bl
-        sq = out["h_sq_sum"].cpu().numpy() / n
-        mean = bsum.mean(axis=0)
-        var = np.maximum(sq - mean * mean, 0.0)
-        ess_site = diagnostics.ess_batch_means(bsum, var, n)
-        th = out["theta"].cpu().numpy()  # (n, chains, 5)
-        per_series = np.empty(S_)
-        for s in range(S_):
-            e_h = 0.0
-            e_th = np.zeros(5)
-            T = int(Ts[s])
-            for j in range(C_):
-                c = s * C_ + j
-                start = C_ * int(off[s]) + j * T
-                e_h = e_h + ess_site[start:start + T]
-                e_th += diagnostics.ess_geyer(th[:, c, :])
-            per_series[s] = min(np.nanmin(e_h), np.nanmin(e_th))
-        acc_rate = float(out["accepted"].float().mean().item())
-        smp.close()
-        return dict(rate=per_series / elapsed, elapsed=elapsed, n=n, dtau=dtau, S=S_t, NW=NW_t,
-                    table=shape_table, acceptance=acc_rate)
-
-    lf_arm = arm(False)
-    om_arm = arm(True)
-    rate, elapsed, n, dtau = lf_arm["rate"], lf_arm["elapsed"], lf_arm["n"], lf_arm["dtau"]
-    S_t, NW_t, shape_table = lf_arm["S"], lf_arm["NW"], lf_arm["table"]
-    total_su = float(Ts.sum()) * C_ * k * n
-    res = {"metric": METRIC, "value": float(np.median(rate)), "unit": "min-ESS/s (median over series)",
-           "n_gpus": 1, "steps": n, "warmup": 500, "ms_per_step": elapsed / n * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32-mixed", "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
-           "config": {"workload": "batched RSV HMC: 512 series, T~U{500..8000}, 4 chains each, "
-                                  f"k=30, dtau jitter {jit}, "
-                                  + ("level move, " if level else "")
-                                  + "FP32 leapfrog, FP64 dH/theta, 2000 sweeps",
-                      "series": S_, "chains_per_series": C_, "k": k, "dtau_jitter": jit,
-                      "level_move": bool(level), "total_sites": int(Ts.sum()),
-                      "sites_per_lane": S_t, "waves_per_tile": NW_t},
-           "autotune_seconds_per_sweep": shape_table,
-           "min_over_series": float(rate.min()), "site_updates_per_s": total_su / elapsed,
-           "acceptance": lf_arm["acceptance"],
-           "dtau_range": [float(dtau.min()), float(dtau.max())],
-           "omelyan": {"integrator": "Omelyan 2nd-order minimum-norm, k=15 (30 force "
-                                     "evaluations, as the leapfrog's k=30)",
-                       "median_min_ess_per_s": float(np.median(om_arm["rate"])),
-                       "min_over_series": float(om_arm["rate"].min()),
-                       "ms_per_step": om_arm["elapsed"] / om_arm["n"] * 1e3,
-                       "acceptance": om_arm["acceptance"],
-                       "dtau_range": [float(om_arm["dtau"].min()), float(om_arm["dtau"].max())],
-                       "sites_per_lane": om_arm["S"], "waves_per_tile": om_arm["NW"]}}
-    if args.cpu_sweeps > 0:
-        import time as _t
-        import oracle
-        s = int(np.argsort(Ts)[S_ // 2])
+    else:
+        S_t, NW_t = shape
+    smp = api.RSVSampler(off, data["y"], data["log_rv"], data["h0"], data["theta0"], max_steps=k_,
+                         seed=3, sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
+    sweep = 0
+    for _ in range(10):  # 10 windows of 50 warm-up sweeps
+        out = smp.sweep(sweep, 50, [(k_, d) for d in dtau], update_theta=True,
+                        record=("delta_h",))
+        sweep += 50
+        dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
+        acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
+        dtau = dtau * np.exp(1.5 * (acc - 0.8))
+    lf = [(k_, d) for d in dtau]
+    smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
+    sweep += 1
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(smp.stream)
+    out = smp.sweep(sweep, n, lf, update_theta=True, record=("theta", "accepted"), batch_len=bl)
+    ev1.record(smp.stream)
+    torch.cuda.synchronize()
+    elapsed = ev0.elapsed_time(ev1) / 1e3
+    bsum = out["h_batch_sum"].cpu().numpy() / bl
+    sq = out["h_sq_sum"].cpu().numpy() / n
+    mean = bsum.mean(axis=0)
+    var = np.maximum(sq - mean * mean, 0.0)
+    ess_site = diagnostics.ess_batch_means(bsum, var, n)
+    th = out["theta"].cpu().numpy()  # (n, chains, 5)
+    per_series = np.empty(S_)
+    for s in range(S_):
+        e_h = 0.0
+        e_th = np.zeros(5)
         T = int(Ts[s])
+        for j in range(C_):
+            c = s * C_ + j
+            start = C_ * int(off[s]) + j * T
+            e_h = e_h + ess_site[start:start + T]
+            e_th += diagnostics.ess_geyer(th[:, c, :])
+        per_series[s] = min(np.nanmin(e_h), np.nanmin(e_th))
+    acc_rate = float(out["accepted"].float().mean().item())
+    smp.close()
+    rate = per_series / elapsed
+    return dict(rate=rate, elapsed=elapsed, n=n, dtau=dtau, S=S_t, NW=NW_t, table=table,
+                acceptance=acc_rate, median=float(np.median(rate)), min=float(rate.min()),
+                ms_per_sweep=elapsed / n * 1e3,
+                site_updates_per_s=float(Ts.sum()) * C_ * k_ * (2 if omelyan else 1) * n / elapsed)
+
+
+def arm_summary(r):
+    return {"median_min_ess_per_s": r["median"], "min_over_series": r["min"],
+            "ms_per_step": r["ms_per_sweep"], "acceptance": r["acceptance"],
+            "site_updates_per_s": r["site_updates_per_s"],
+            "dtau_range": [float(r["dtau"].min()), float(r["dtau"].max())],
+            "sites_per_lane": r["S"], "waves_per_tile": r["NW"]}
+
+
+def run_batched(args):
+    """512 series, T ~ U{500..8000}, per-series theta, 4 chains each, k = 30,
+    FP32-mixed leapfrog, FP64 dH/theta; per-series dtau adapted to ~0.8
+    acceptance over 500 warm-up sweeps; 2000 measured sweeps with batch means
+    (50 batches of 40) accumulated on the device.  value = median over series
+    of min-ESS/s under the paper's sampler (fixed dtau, Gibbs theta); beside
+    it the extensions: step-size jitter 0.5 with the level move, and
+    Omelyan's integrator at the same 30 force evaluations."""
+    k = 30
+    data = batched_data()
+    Ts = np.diff(data["offsets"])
+    jit = jitter_of(args, 0.0)
+    level = level_of(args, False)
+    main_arm = batched_arm(data, k, jit, level)
+    ext = batched_arm(data, k, 0.5, True, shape=(main_arm["S"], main_arm["NW"]))
+    om = batched_arm(data, k, 0.5, True, omelyan=True)
+    res = {"metric": METRIC, "value": main_arm["median"],
+           "unit": "min-ESS/s (median over series)", "n_gpus": 1, "steps": main_arm["n"],
+           "warmup": 500, "ms_per_step": main_arm["ms_per_sweep"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed",
+           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": "batched RSV HMC: 512 series, T~U{500..8000}, 4 chains each, "
+                                  f"k=30, FP32 leapfrog, FP64 dH/theta, 2000 sweeps"
+                                  + (f", dtau jitter {jit}" if jit else "")
+                                  + (", level move" if level else ""),
+                      "series": int(Ts.size), "chains_per_series": 4, "k": k, "dtau_jitter": jit,
+                      "level_move": bool(level), "total_sites": int(Ts.sum()),
+                      "sites_per_lane": main_arm["S"], "waves_per_tile": main_arm["NW"]},
+           "autotune_seconds_per_sweep": main_arm["table"],
+           "min_over_series": main_arm["min"], "site_updates_per_s": main_arm["site_updates_per_s"],
+           "acceptance": main_arm["acceptance"],
+           "dtau_range": [float(main_arm["dtau"].min()), float(main_arm["dtau"].max())],
+           "extension_jitter_0.5_level_move": arm_summary(ext),
+           "extension_omelyan_k15_jitter_0.5_level_move": arm_summary(om)}
+    if args.cpu_sweeps > 0:
+        res["cpu_baseline"] = batched_cpu_baseline(data, k, main_arm["dtau"], jit, level)
+    return res
+
+
+def batched_cpu_baseline(data, k, dtau, jit, level, n_sweeps=25):
+    """The oracle on all host cores, one chain per thread (OpenMP-style over
+    chains): the 4 chains of the series of median length, and more series of
+    similar length up to one chain per core, n_sweeps sweeps each."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    off, C_ = data["offsets"], data["C"]
+    Ts = np.diff(off)
+    order = np.argsort(np.abs(Ts - np.median(Ts)))
+    cores, nproc, model = host_cpu()
+    jobs = []
+    for s in order:
+        for j in range(C_):
+            if len(jobs) < max(cores, C_):
+                jobs.append((int(s), j))
+
+    def one(job):
+        s, j = job
         y2 = data["y"][off[s]:off[s + 1]] ** 2
         r = data["log_rv"][off[s]:off[s + 1]]
-        t0 = _t.perf_counter()
-        for j in range(C_):
-            oracle.run(data["h_true"][off[s]:off[s + 1]], data["thetas"][s], y2, r, k,
-                       float(dtau[s]), 25, seed=3, chain=s * C_ + j, jitter=jit,
-                       moves=oracle.MOVE_LEVEL if level else 0)
-        dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": T * k * 25 * C_ / dt, "unit": "site-updates/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": f"4 chains x 25 sweeps of the median-length series "
-                                         f"(T={T}), FP64 serial C", "seconds": dt}
-    return res
+        oracle.run(data["h_true"][off[s]:off[s + 1]], data["thetas"][s], y2, r, k,
+                   float(dtau[s]), n_sweeps, seed=3, chain=s * C_ + j, jitter=jit,
+                   moves=oracle.MOVE_LEVEL if level else 0)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(one, jobs))
+    dt = time.perf_counter() - t0
+    su = sum(int(Ts[s]) for s, _ in jobs) * k * n_sweeps
+    return {"value": su / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(jobs)} chains of the series closest to the median length "
+                      f"(T {int(Ts[order[0]])}..{int(max(Ts[s] for s, _ in jobs))}), "
+                      f"{n_sweeps} sweeps each, one chain per thread, FP64 serial C per chain",
+            "seconds": dt, "nproc": nproc, "cpu_model": model}
 
 
 def run_mass(args):
@@ -647,17 +732,27 @@ def main():
     kern_avg = kern_ms / 1e3 / max(n_rec, 1)
     traj_rate = float(T) * k / kern_avg
     isa = isa_figures(args.precision, S, NW)
-    peak = FP64_PEAK_TFLOPS if args.precision == "f64" else FP32_PEAK_TFLOPS
-    roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
-            "traffic": None, "kernel": "k_traj", "avg_launch_ms": kern_avg * 1e3,
-            "launches": n_rec}
+    # ALU roofline of the trajectory kernel: VALU lane-instructions issued per
+    # second by its leapfrog loop (instructions per site-update read from the
+    # gfx950 assembly x site-updates/s) against the issue peak
+    roof = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_T,
+            "unit": "T VALU lane-instructions/s", "frac": None, "traffic": None,
+            "kernel": "k_traj", "avg_launch_ms": kern_avg * 1e3, "launches": n_rec,
+            "peak_is": "256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one VALU instruction per lane "
+                       "per clock (the nominal clock; the kernel runs near 2.07 GHz)"}
     if isa:
-        # FMA-equivalent rate of the kernel's VALU issue: 2 x (VALU instructions per
-        # site-update in the leapfrog loop, from the ISA) x site-updates / s.
-        per_unit = 2.0 * isa["valu_per_site_update"]
-        roof["achieved"] = per_unit * traj_rate / 1e12
-        roof["frac"] = roof["achieved"] / peak
-        roof["flop_per_site_update"] = per_unit
+        roof["achieved"] = isa["valu_per_site_update"] * traj_rate / 1e12
+        roof["frac"] = roof["achieved"] / VALU_PEAK_T
+        roof["valu_per_site_update"] = isa["valu_per_site_update"]
+        # the method's floating-point work alone (an FMA counts 2)
+        flop_peak = FP64_PEAK_TFLOPS if args.precision == "f64" else FP32_PEAK_TFLOPS_UNPACKED
+        flops = isa["flop_per_site_update"] * traj_rate / 1e12
+        roof["flops"] = {"achieved": flops, "peak": flop_peak, "unit": "TFLOP/s",
+                         "frac": flops / flop_peak,
+                         "flop_per_site_update": isa["flop_per_site_update"],
+                         "peak_is": ("FP64 vector" if args.precision == "f64" else
+                                     "FP32 vector without packed FP32 (disabled in this build; "
+                                     "157.3 TFLOP/s needs it)")}
     tr = measured_traffic(args.precision, S, NW, T, k)
     if tr:
         roof["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
@@ -690,10 +785,31 @@ def main():
                                  "GB/s": stream_gbs, "frac_of_hbm_peak": stream_gbs / HBM_PEAK_GBS},
         "wall_s": wall,
     }
+    smp.close()
     if args.cpu_sweeps > 0:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(y, lr, h_true, theta, k, dtau, args.cpu_sweeps,
                                            args.seed, T)
+    if not args.no_extras:
+        # min-ESS/s of the paper's sampler on the single-series and batched
+        # workloads, in the same run
+        print("[bench] single-series min-ESS/s", file=sys.stderr, flush=True)
+        g, r = small_chain(0.0, False, args.cpu_sweeps > 0)
+        res["single_series_min_ess"] = {
+            "workload": "one series T=1000, k=20, dtau=0.05, FP64, 500 burn-in + 5000 sweeps, "
+                        "theta every sweep (the paper's sampler)",
+            "min_ess_per_s": g["min_ess_per_s"], "min_ess": g["min_ess"],
+            "min_ess_h": g["min_ess_h"], "min_ess_theta": g["min_ess_theta"],
+            "acceptance": g["acceptance"], "ms_per_sweep": g["seconds"] / 5000 * 1e3,
+            "cpu_baseline": r}
+        print("[bench] batched min-ESS/s", file=sys.stderr, flush=True)
+        bd = batched_data()
+        b = batched_arm(bd, 30, 0.0, False, shape=(8, 1))
+        res["batched_min_ess"] = {
+            "workload": "512 series, T~U{500..8000}, 4 chains each, k=30, FP32 leapfrog, FP64 "
+                        "dH/theta, dtau adapted to ~0.8, 2000 sweeps, 50 batch means (the "
+                        "paper's sampler), tile shape 8 x 1",
+            **arm_summary(b), "min_ess_per_s_median": b["median"], "min_ess_per_s_min": b["min"]}
     print(json.dumps(res), flush=True)
 
 

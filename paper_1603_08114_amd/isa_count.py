@@ -4,7 +4,9 @@ Compiles csrc/rsv_traj_f64.hip and csrc/rsv_traj_f32.hip to device assembly, fin
 kernel (identity mass, RSV terms) the loop that carries the DPP
 lane shifts -- one leapfrog step over a lane's S sites -- and counts its VALU
 instructions.  Dividing by S gives VALU instructions per site-update, the
-per-unit figure of the ALU roofline.  Writes isa_counts.json next to this file.
+per-unit figure of the ALU roofline, and its floating-point operations (an
+FMA counts 2).  Writes isa_counts.json next to this file.  A measurement
+tool: it reads the AMD assembly of this library's own gfx950 build.
 """
 import json
 import os
@@ -100,9 +102,15 @@ def count(asm: str) -> dict:
         # 32-bit word, so the loop body holds `steps` unrolled steps
         dpp = sum(v for k, v in ops.items() if "_dpp" in k)
         steps = dpp // (4 if prec == "f64" else 2)
+        # floating-point operations of the method's arithmetic: a fused
+        # multiply-add counts 2, an add, subtract, multiply or exponential 1
+        flop = sum(v * (2 if ("fma" in k or "fmac" in k) else 1) for k, v in ops.items()
+                   if k.startswith("v_") and prec in k
+                   and any(w in k for w in ("fma", "add", "sub", "mul", "exp")))
         table[f"{prec}_S{S}_W{NW}"] = dict(
             loop_instructions=sum(ops.values()), steps_per_loop=steps,
             valu_per_site_update=valu / (S * steps), fp_valu_per_site_update=fp / (S * steps),
+            flop_per_site_update=flop / (S * steps),
             **descriptor(asm, name), top_ops=dict(ops.most_common(12)))
     return table
 
