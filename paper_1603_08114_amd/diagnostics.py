@@ -70,3 +70,52 @@ def ess_batch_means(batch_means, variance, n_draws: int) -> np.ndarray:
 def mcse_mean(x) -> np.ndarray:
     x = np.asarray(x, dtype=np.float64)
     return np.sqrt(x.var(axis=0) / ess_geyer(x))
+
+
+# --- comparing two samplers' posterior moments -----------------------------------
+# Each side runs k independent chains from the same start; the moments of a
+# quantity are the grand mean of its per-chain means (or variances), with a
+# standard error from the chain-to-chain spread.  That error needs no model
+# of the autocorrelation, and the comparison holds before convergence too:
+# two correct implementations of one Markov kernel (or two exact kernels at
+# equilibrium) give the same distribution of the chain state after each
+# sweep from the same start.
+
+def spread_summary(per_chain) -> tuple:
+    """Grand mean, its standard error and the number of chains, from per-chain
+    values (k, d) of a statistic."""
+    v = np.asarray(per_chain, dtype=np.float64)
+    k = v.shape[0]
+    return v.mean(axis=0), v.std(axis=0, ddof=1) / np.sqrt(k), k
+
+
+def welch_p(per_chain_a, per_chain_b):
+    """Two-sided Welch-t p-values (and z) for equal grand means of a statistic
+    per quantity, from per-chain values (k_a, d) and (k_b, d)."""
+    from scipy import stats
+    ma, sa, ka = spread_summary(per_chain_a)
+    mb, sb, kb = spread_summary(per_chain_b)
+    va, vb = sa * sa, sb * sb
+    se = np.sqrt(va + vb)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z = (ma - mb) / se
+        df = (va + vb) ** 2 / (va * va / (ka - 1) + vb * vb / (kb - 1))
+    p = 2.0 * stats.t.sf(np.abs(z), np.where(np.isfinite(df), df, ka + kb - 2))
+    return z, p
+
+
+def moment_rule(p, alpha_family=0.01, tail=0.0027):
+    """The multiple-comparison rule for N quantities compared at once: the
+    fraction of p-values below `tail` (the two-sided 3-sigma level) may
+    exceed `tail` by at most three binomial standard errors, and the smallest
+    p-value must be at least alpha_family / N (Bonferroni).  Returns
+    (passed, summary)."""
+    p = np.asarray(p, dtype=np.float64).ravel()
+    p = p[np.isfinite(p)]
+    n = p.size
+    frac = float(np.mean(p < tail))
+    limit = tail + 3.0 * np.sqrt(tail * (1.0 - tail) / n)
+    p_min = float(p.min())
+    ok = frac <= limit and p_min >= alpha_family / n
+    return ok, {"n": int(n), "frac_p_below_0.0027": frac, "frac_limit": float(limit),
+                "min_p": p_min, "min_p_limit": alpha_family / n}
