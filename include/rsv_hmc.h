@@ -198,8 +198,9 @@ typedef struct rsv_ctx rsv_ctx;
 /* Bytes of device workspace rsv_hmc_init needs for this problem (0 if the
  * problem is invalid; see rsv_last_error): the proposal state buffer, y^2
  * (and FP32 copies on the mixed path), the tile descriptors and per-tile
- * partials, per-chain selectors and level shifts, and 16 bytes per data site
- * for the diagonal-mass tables (reserved whether or not a mass is given). */
+ * partials, per-chain selectors and level shifts, and one entry of the
+ * state's type per data site for the diagonal-mass table (sqrt(m_t), 8 bytes
+ * in FP64, 4 in FP32; reserved whether or not a mass is given). */
 size_t rsv_hmc_workspace_bytes(const rsv_problem *pb);
 
 /* Number of state entries, C * offsets[S] (0 if invalid). */
@@ -213,7 +214,10 @@ int64_t rsv_hmc_state_size(const rsv_problem *pb);
  *   log_mass device, offsets[S] floats: log of the diagonal mass m_t of each
  *            series-site (shared by the chains of a series), or NULL for
  *            m = 1 (the paper's kinetic term 1/2 sum p^2).  Read once here:
- *            1/m_t and sqrt(m_t) are kept in the workspace.
+ *            sqrt(m_t) is kept in the workspace in the state's precision
+ *            (rounded to FP32 on the mixed path; that value defines the
+ *            mass: momenta are drawn as z sqrt(m_t) and the kinetic term
+ *            uses 1/m_t formed from it in FP64).
  *   workspace, ws_bytes  device scratch of at least rsv_hmc_workspace_bytes.
  *   hip_stream  hipStream_t to enqueue on (NULL = the null stream).
  * Validates the problem on the host and the data, h and theta on the device
@@ -231,7 +235,7 @@ rsv_status rsv_hmc_init(rsv_ctx **out, const rsv_problem *pb, void *h, rsv_theta
  * which that device keeps until the process ends.  Nothing is allocated on
  * the device here or in later calls on the context.  Limit: problems whose
  * rsv_hmc_workspace_bytes exceeds RSV_STATIC_WORKSPACE_BYTES get
- * RSV_ENOMEM (e.g. one FP64 chain of more than about 830 000 sites).
+ * RSV_ENOMEM (e.g. one FP64 chain of more than about 1 040 000 sites).
  * Sharing: every static context on a device uses that device's one array,
  * and each rsv_hmc_init_static takes it over: calls on an older static
  * context of the device then return RSV_ESTATE.  The array keeps the last

@@ -71,7 +71,10 @@ class rsv_trace(C.Structure):
                 ("batch_len", C.c_int32), ("reserved", C.c_int32)]
 
 
-def load(path: str = LIB_PATH) -> C.CDLL:
+def load(path: str | None = None) -> C.CDLL:
+    """The HIP library at `path`, by default the module's LIB_PATH as it is
+    at the call (a caller may point LIB_PATH at another build first)."""
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
             f"HIP library {path} is not built; run `python -m paper_1603_08114_amd.build` "

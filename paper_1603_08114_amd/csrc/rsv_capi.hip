@@ -101,7 +101,7 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_kicks) {
 
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
-           edge = 0, accept = 0, shift = 0, mass_inv = 0, mass_sqrt = 0, acc = 0, counters = 0,
+           edge = 0, accept = 0, shift = 0, mass_sqrt = 0, acc = 0, counters = 0,
            bins = 0, bin_chains = 0, bin_tiles = 0, total = 0;
     int32_t max_tiles = 0;
 };
@@ -188,8 +188,7 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->edge = take(n_chains * kEdge * sizeof(double));
     L->accept = take(n_chains * sizeof(int32_t));
     L->shift = take(n_chains * sizeof(double));
-    L->mass_inv = take(n_data * sizeof(double));
-    L->mass_sqrt = take(n_data * sizeof(double));
+    L->mass_sqrt = take(n_data * elem);
     L->acc = take(2 * n_state * sizeof(float));
     L->counters = take(kNumCounters * sizeof(uint32_t));
     L->bins = take(n_chains * sizeof(BinDesc));
@@ -228,8 +227,8 @@ struct rsv_ctx {
     double* edge = nullptr;
     int32_t* accept = nullptr;  // per chain: 1 if its current state is in h_prop
     double* shift = nullptr;    // per chain: pending level shift of the current state
-    double* mass_inv = nullptr;   // per data site 1/m_t (with a diagonal mass)
-    double* mass_sqrt = nullptr;  // per data site sqrt(m_t)
+    void* mass_sqrt = nullptr;    // per data site sqrt(m_t) (with a diagonal mass), in the
+                                  // state's precision
     float* acc_f = nullptr;       // per state entry: FP32 batch sum, then batch sum of squares
     uint32_t* counters = nullptr;
     BinDesc* bins = nullptr;          // resident sweeps: bins of chains, one per block
@@ -447,8 +446,7 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     }
     a.y2_d = c->y2_d;
     a.lrv_d = c->pb.log_rv;
-    a.mass_inv = c->log_mass ? c->mass_inv : nullptr;
-    a.mass_sqrt = c->log_mass ? c->mass_sqrt : nullptr;
+    a.mass_sqrt = c->log_mass ? static_cast<const R*>(c->mass_sqrt) : nullptr;
     a.p0 = p0;
     a.seed = c->pb.seed;
     a.sweep = sweep;
@@ -657,8 +655,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->edge = reinterpret_cast<double*>(c->ws + L.edge);
     c->accept = reinterpret_cast<int32_t*>(c->ws + L.accept);
     c->shift = reinterpret_cast<double*>(c->ws + L.shift);
-    c->mass_inv = reinterpret_cast<double*>(c->ws + L.mass_inv);
-    c->mass_sqrt = reinterpret_cast<double*>(c->ws + L.mass_sqrt);
+    c->mass_sqrt = c->ws + L.mass_sqrt;
     c->acc_f = reinterpret_cast<float*>(c->ws + L.acc);
     c->counters = reinterpret_cast<uint32_t*>(c->ws + L.counters);
     c->bins = reinterpret_cast<BinDesc*>(c->ws + L.bins);
@@ -683,8 +680,8 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     RSV_HIP_INIT(launch_prepare(c->stream, pb->y, pb->log_rv, c->n_data, c->y2_d, c->y2_f,
                                 c->lrv_f));
     if (log_mass)
-        RSV_HIP_INIT(launch_mass_tables(c->stream, log_mass, c->n_data, c->mass_inv,
-                                        c->mass_sqrt));
+        RSV_HIP_INIT(launch_mass_table(c->stream, log_mass, c->n_data, c->mass_sqrt,
+                                       pb->precision));
     RSV_HIP_INIT(launch_validate(c->stream, pb->y, pb->log_rv, c->n_data, h, c->n_state,
                                  pb->precision, c->counters));
     std::vector<rsv_theta> th(c->n_chains);
@@ -760,7 +757,7 @@ rsv_status rsv_hmc_momenta(rsv_ctx* c, uint64_t sweep, double* p_out) {
     if (rsv_status nf = nonfinite_reported(c); nf != RSV_OK) return nf;
     if (!p_out) return fail(RSV_EINVAL, "p_out is NULL");
     RSV_HIP(launch_momenta(c->stream, c->chains, c->n_chains, c->max_T,
-                           c->log_mass ? c->mass_sqrt : nullptr, c->pb.seed,
+                           c->log_mass ? c->mass_sqrt : nullptr, c->pb.precision, c->pb.seed,
                            sweep, p_out));
     return RSV_OK;
 }

@@ -65,8 +65,7 @@ struct TrajArgs {
     const R* lrv;               // ln RV_t in R
     const double* y2_d;         // FP64 copies for dH and the statistics
     const double* lrv_d;
-    const double* mass_inv;     // per data site 1/m_t, or nullptr (identity mass)
-    const double* mass_sqrt;    // per data site sqrt(m_t), with mass_inv
+    const R* mass_sqrt;         // per data site sqrt(m_t) in R, or nullptr (identity mass)
     const double* p0;           // momentum override (per state entry) or nullptr
     uint64_t seed;
     uint64_t sweep;
@@ -183,12 +182,13 @@ hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
                         const void* h_b, const int32_t* state_sel, const double* shift,
                         const double* y2_d, const double* lrv_d, double* partials,
                         double* chain_edge, int precision);
-// 1/m_t and sqrt(m_t) from ln m_t (once, at init).
-hipError_t launch_mass_tables(hipStream_t st, const float* log_mass, int64_t n, double* inv,
-                              double* sqrt_m);
+// sqrt(m_t) from ln m_t (once, at init), as an FP64 table (precision
+// RSV_F64) or an FP32 table (RSV_F32_MIXED).
+hipError_t launch_mass_table(hipStream_t st, const float* log_mass, int64_t n, void* sqrt_m,
+                             int precision);
 hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
-                          int32_t max_T, const double* mass_sqrt, uint64_t seed, uint64_t sweep,
-                          double* p_out);
+                          int32_t max_T, const void* mass_sqrt, int precision, uint64_t seed,
+                          uint64_t sweep, double* p_out);
 hipError_t launch_count_nonfinite(hipStream_t st, const void* h, int64_t n, int precision,
                                   uint32_t* counter);
 

@@ -86,23 +86,24 @@ __global__ void k_clear_sel(int32_t* state_sel, double* shift, int32_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal mass tables: 1/m_t and sqrt(m_t) from the caller's ln m_t.
+// Diagonal mass table: sqrt(m_t) from the caller's ln m_t, in the precision
+// of the state (FP64, or FP32 on the mixed path: 4 bytes per site).  The
+// trajectory kernel forms 1/m_t from it; the stored value defines the mass.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mass_tables(const float* log_mass, int64_t n,
-                                                     double* inv, double* sqrt_m) {
+template <typename M>
+__global__ __launch_bounds__(256) void k_mass_table(const float* log_mass, int64_t n,
+                                                    M* sqrt_m) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
-         t += stride) {
-        const double l = static_cast<double>(log_mass[t]);
-        inv[t] = exp_fast(-l);
-        sqrt_m[t] = exp_fast(0.5 * l);
-    }
+         t += stride)
+        sqrt_m[t] = static_cast<M>(exp_fast(0.5 * static_cast<double>(log_mass[t])));
 }
 
 // ---------------------------------------------------------------------------
 // Standalone momentum refresh (same streams as the trajectory kernel).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const double* mass_sqrt,
+template <typename M>
+__global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const M* mass_sqrt,
                                                  uint64_t seed, uint64_t sweep, double* p_out) {
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const 
         for (int q = 0; q < 4; ++q) {
             const int t = 4 * g + q;
             if (t >= cd.T) break;
-            const double sm = mass_sqrt ? mass_sqrt[cd.d_off + t] : 1.0;
+            const double sm = mass_sqrt ? static_cast<double>(mass_sqrt[cd.d_off + t]) : 1.0;
             p_out[cd.h_off + t] = z[q] * sm;
         }
     }
@@ -302,19 +303,29 @@ hipError_t launch_stats(hipStream_t st, const TileDesc* tiles, int32_t n_tiles,
     return hipGetLastError();
 }
 
-hipError_t launch_mass_tables(hipStream_t st, const float* log_mass, int64_t n, double* inv,
-                              double* sqrt_m) {
+hipError_t launch_mass_table(hipStream_t st, const float* log_mass, int64_t n, void* sqrt_m,
+                             int precision) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mass_tables, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, log_mass, n,
-                       inv, sqrt_m);
+    const dim3 g(grid_for(n, 256, 4096)), b(256);
+    if (precision == RSV_F64)
+        hipLaunchKernelGGL(k_mass_table<double>, g, b, 0, st, log_mass, n,
+                           static_cast<double*>(sqrt_m));
+    else
+        hipLaunchKernelGGL(k_mass_table<float>, g, b, 0, st, log_mass, n,
+                           static_cast<float*>(sqrt_m));
     return hipGetLastError();
 }
 
 hipError_t launch_momenta(hipStream_t st, const ChainDesc* chains, int32_t n_chains,
-                          int32_t max_T, const double* mass_sqrt, uint64_t seed, uint64_t sweep,
-                          double* p_out) {
+                          int32_t max_T, const void* mass_sqrt, int precision, uint64_t seed,
+                          uint64_t sweep, double* p_out) {
     const dim3 g(grid_for((max_T + 3) / 4, 256, 1024), n_chains), b(256);
-    hipLaunchKernelGGL(k_momenta, g, b, 0, st, chains, mass_sqrt, seed, sweep, p_out);
+    if (precision == RSV_F64)
+        hipLaunchKernelGGL(k_momenta<double>, g, b, 0, st, chains,
+                           static_cast<const double*>(mass_sqrt), seed, sweep, p_out);
+    else
+        hipLaunchKernelGGL(k_momenta<float>, g, b, 0, st, chains,
+                           static_cast<const float*>(mass_sqrt), seed, sweep, p_out);
     return hipGetLastError();
 }
 

@@ -162,6 +162,16 @@ struct Stage {
     static constexpr int n = on ? 3 * S * 64 * NW : 1;
 };
 
+// 1/m_t from the stored sqrt(m_t), in FP64 with a correctly rounded division:
+// the momentum is drawn as z sqrt(m_t), so the kinetic term p^2 / (2 m_t)
+// formed from this value is the one of the law the momentum follows (to
+// FP64 rounding), and the same value serves both ends of the trajectory.
+template <typename R>
+__device__ __forceinline__ double inv_mass(R sqrt_m) {
+    const double s = static_cast<double>(sqrt_m);
+    return 1.0 / (s * s);
+}
+
 template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET, bool STAGE>
 __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW>& sh,
                                           const int tile_id, const int wv, const int lane,
@@ -188,7 +198,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const R db = static_cast<R>(dk * beta);
     const R mu_r = static_cast<R>(mu), phi_r = static_cast<R>(phi);
 
-    R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1];
+    // with a diagonal mass: sqrt(m_t) per site (read with the state, so that
+    // its latency overlaps the momentum draw, and kept for the dH pass) and
+    // the per-site drift step dt / m_t
+    R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1], msq[MASS ? S : 1];
     double kin0 = 0.0;  // kinetic energy of the exact sites at the start
 
     const bool in_b = A.state_sel[td.chain] != 0;
@@ -197,11 +210,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     R* hp = (in_b ? const_cast<R*>(A.h_a) : A.h_b) + cd.h_off;
     const R* y2 = A.y2 + cd.d_off;
     const R* lr = A.lrv + cd.d_off;
+    const R* msq_tab = MASS ? A.mass_sqrt + cd.d_off : nullptr;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         const bool live = t < T;
         h[j] = live ? state_at(hc, t, shift) : R(0);
+        if constexpr (MASS) msq[j] = live ? msq_tab[t] : R(1);
         const double yy = live ? static_cast<double>(y2[t]) : 0.0;
         const double rr = live ? static_cast<double>(lr[t]) : 0.0;
         dc[j] = static_cast<R>(-dk * (c_base - rr * inv_su));
@@ -242,8 +257,6 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     }
 
     // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
-    const double* minv = MASS ? A.mass_inv + cd.d_off : nullptr;
-    const double* msq = MASS ? A.mass_sqrt + cd.d_off : nullptr;
     if (A.p0) {
         const double* p0 = A.p0 + cd.h_off;
 #pragma unroll
@@ -259,33 +272,23 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
                       static_cast<uint64_t>(td.chain), kTagMomentum, u);
             gauss_pair(u[0], u[1], z[0], z[1]);
             gauss_pair(u[2], u[3], z[2], z[3]);
-            // the mass table is read only after this block's normals exist:
-            // loads hoisted above the generator would hold registers through it
-            if constexpr (MASS) asm volatile("" ::: "memory");
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
                 const int t = t0 + j;
                 double pm = z[q];
-                if constexpr (MASS) pm *= (t < T) ? msq[t] : 1.0;
+                if constexpr (MASS) pm *= static_cast<double>(msq[MASS ? j : 0]);
                 p[j] = (t < T) ? static_cast<R>(pm) : R(0);
             }
-        }
-    }
-    if constexpr (MASS) {
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
-            dtm[j] = static_cast<R>(dt * ((t < T) ? minv[t] : 1.0));
         }
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
+        const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
+        if constexpr (MASS) dtm[j] = static_cast<R>(dt * im);
         if (t >= td.a && t < td.b) {
             const double pj = static_cast<double>(p[j]);
-            const double im = MASS ? minv[t] : 1.0;
             kin0 += 0.5 * pj * pj * im;
         }
     }
@@ -468,16 +471,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
-    // 1/m_t is read again here rather than kept live across the leapfrog loop
-    const double* minv_again = minv;
-    if constexpr (MASS) asm volatile("" : "+v"(minv_again));
     DhSums D = {-kin0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, 0.0, 0.0};
     double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         if (t < td.a || t >= td.b) continue;
-        const double im = MASS ? minv_again[t] : 1.0;
+        const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
         const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
         const double yy = RET ? (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) : 0.0;
         const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + (j < S - 1)]);
@@ -541,7 +541,9 @@ __device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
     __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
     __shared__ double stage_all[kTilesPerBlock][St::n];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv_blk = threadIdx.x / kWave;
+    // wavefront index in the block: uniform, so the tile index and everything
+    // read through it stay in scalar registers
+    const int wv_blk = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int w = blockIdx.x * kTilesPerBlock + wv_blk / NW;
     if (w >= A.n_list) return;  // uniform over the tile's wavefronts
     const int tile_id = A.tile_first + w;
@@ -561,13 +563,13 @@ void k_traj(TrajArgs<R> A) {
     traj_launch_body<R, S, NW, false, RET>(A);
 }
 
-// Diagonal mass.  Its momentum draw keeps more values live than the leapfrog
-// loop needs; for S <= 8 the register cap of four waves per SIMD moves the
-// overflow to scratch in that once-per-trajectory phase, not in the loop
-// (S = 16 needs more than the cap in the loop itself and is left uncapped).
+// Diagonal mass.  Shapes with 32 bytes of state per lane (FP64 S = 4, FP32
+// S = 8) are held to four waves per SIMD (128 registers), which they fit
+// without spilling; the larger shapes need more than that in the leapfrog
+// loop itself and are left uncapped (two or three waves per SIMD).
 template <typename R, int S, int NW, bool RET>
 __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW)
-__attribute__((amdgpu_waves_per_eu(S <= 8 ? 4 : 1)))
+__attribute__((amdgpu_waves_per_eu(S * sizeof(R) <= 32 ? 4 : 1)))
 void k_traj_mass(TrajArgs<R> A) {
     traj_launch_body<R, S, NW, true, RET>(A);
 }

@@ -123,7 +123,7 @@ def test_autotune_cache_key_buckets():
 def test_static_workspace_limit_checked_on_the_host():
     """rsv_hmc_init_static refuses a problem whose workspace exceeds the
     static array before any device call (no GPU needed)."""
-    big = _pb([0, 900_000], max_steps=50)
+    big = _pb([0, 1_200_000], max_steps=50)
     assert api.rsv_hmc_workspace_bytes(big) > _lib.RSV_STATIC_WORKSPACE_BYTES
     ctx = C.c_void_p()
     st = api.lib().rsv_hmc_init_static(C.byref(ctx), C.byref(big.struct()), None, None, None,

@@ -70,7 +70,7 @@ def test_static_workspace_matches_caller_workspace(precision, flags):
 
 
 def test_static_workspace_rejects_a_problem_beyond_its_size():
-    T = 900_000  # FP64: about 35 MiB of workspace, more than the 32 MiB array
+    T = 1_200_000  # FP64: about 37 MiB of workspace, more than the 32 MiB array
     y, r, h = synth.simulate_rsv_long(T, synth.THETA_STAR, 1)
     with pytest.raises(api.RSVError) as e:
         api.RSVSampler([0, T], y, r, h, synth.THETA_STAR, max_steps=50, static_workspace=True)
