@@ -217,7 +217,9 @@ int64_t rsv_hmc_state_size(const rsv_problem *pb);
  *            sqrt(m_t) is kept in the workspace in the state's precision
  *            (rounded to FP32 on the mixed path; that value defines the
  *            mass: momenta are drawn as z sqrt(m_t) and the kinetic term
- *            uses 1/m_t formed from it in FP64).
+ *            uses 1/m_t formed from it in FP64).  A site whose ln m_t is
+ *            not finite or outside [-80, 80] takes m_t = 1 (the identity
+ *            mass; the chain stays exact for any fixed positive mass).
  *   workspace, ws_bytes  device scratch of at least rsv_hmc_workspace_bytes.
  *   hip_stream  hipStream_t to enqueue on (NULL = the null stream).
  * Validates the problem on the host and the data, h and theta on the device

@@ -89,14 +89,22 @@ __global__ void k_clear_sel(int32_t* state_sel, double* shift, int32_t n) {
 // Diagonal mass table: sqrt(m_t) from the caller's ln m_t, in the precision
 // of the state (FP64, or FP32 on the mixed path: 4 bytes per site).  The
 // trajectory kernel forms 1/m_t from it; the stored value defines the mass.
+// A site whose ln m_t is not finite, or whose sqrt(m_t) or 1/m_t would
+// overflow or vanish in the state's precision, takes the identity mass
+// m_t = 1 (any fixed positive mass keeps the chain exact).
 // ---------------------------------------------------------------------------
 template <typename M>
 __global__ __launch_bounds__(256) void k_mass_table(const float* log_mass, int64_t n,
                                                     M* sqrt_m) {
+    // |ln m| <= 80 keeps sqrt(m) and 1/m normal in FP32
+    constexpr double kMaxLogMass = 80.0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
-         t += stride)
-        sqrt_m[t] = static_cast<M>(exp_fast(0.5 * static_cast<double>(log_mass[t])));
+         t += stride) {
+        const double l = static_cast<double>(log_mass[t]);
+        const bool ok = l >= -kMaxLogMass && l <= kMaxLogMass;  // false for NaN
+        sqrt_m[t] = ok ? static_cast<M>(exp_fast(0.5 * l)) : M(1);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,10 @@
    the first half of warm-up, from the data and the theta reached then (a
    fixed mass that depends only on data and a frozen theta keeps the
    Metropolis test exact), and adapt dtau under it for the second half.
+   Identity mass is the fallback for a series whose network output is not
+   finite at some site, or whose warm-up acceptance under the learned mass
+   stays below 0.5 (the library itself also takes m_t = 1 at any site whose
+   ln m_t is not finite).
 
 Efficiency per series: min over {h_t} and theta of the ESS summed over the
 series' chains, divided by the wall time of the measured sweeps.  ESS of h_t
@@ -30,19 +34,38 @@ def _series_view(off, C):
     return Ts, np.concatenate([[0], np.cumsum(Ts * C)])
 
 
-def adapt(smp, lf_k, dtau, sweep, windows, n_series, C, win=50, target=0.8, gain=1.5,
+def adapt(smp, lf_k, dtau, sweep, n_sweeps, n_series, C, win=25, target=0.8, gain=2.0,
           update_theta=True):
-    """Per-series dtau: after each window of `win` sweeps,
-    dtau *= exp(gain (mean min(1, e^-dH) - target))."""
-    for _ in range(windows):
+    """Per-series dtau by stochastic approximation on ln dtau: after window i
+    of `win` sweeps, ln dtau += gain / sqrt(i + 1) * (a - target), a the mean
+    Metropolis probability min(1, e^-dH) over the window's trajectories of
+    the series' chains.  Returns dtau, the next sweep index, the acceptance
+    probability of the last window under the returned dtau's predecessor,
+    and the last theta of every chain."""
+    n_win = max(1, n_sweeps // win)
+    for i in range(n_win):
         out = smp.sweep(sweep, win, [(lf_k, d) for d in dtau], update_theta=update_theta,
                         record=("delta_h", "theta"))
         sweep += win
         dh = out["delta_h"].cpu().numpy().reshape(win, n_series, C)
         acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
-        dtau = dtau * np.exp(gain * (acc - target))
+        dtau = dtau * np.exp(gain / np.sqrt(i + 1.0) * (acc - target))
         last_theta = out["theta"].cpu().numpy()
     return dtau, sweep, acc, last_theta
+
+
+def series_log_mass(log_m, off):
+    """Per-series identity fallback: a series any of whose log m_t is not
+    finite takes the identity mass (log m = 0) at every site.  Returns the
+    array and the indices of the series that fell back."""
+    lm = np.asarray(log_m, dtype=np.float32).copy()
+    bad = []
+    for s in range(len(off) - 1):
+        seg = lm[off[s]:off[s + 1]]
+        if not np.all(np.isfinite(seg)):
+            seg[:] = 0.0
+            bad.append(s)
+    return lm, bad
 
 
 def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
@@ -68,6 +91,7 @@ def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
     th = out["theta"].cpu().numpy()
     S = len(Ts)
     ess_h = np.empty(S)
+    ess_h_mean = np.empty(S)
     ess_th = np.empty(S)
     pooled_mean = torch.empty(int(off[-1]), dtype=torch.float64, device=mean.device)
     pooled_var = torch.empty_like(pooled_mean)
@@ -76,6 +100,7 @@ def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
         seg = slice(int(cstart[s]), int(cstart[s + 1]))
         e = ess[seg].reshape(C, T).sum(0)
         ess_h[s] = float(e.min())
+        ess_h_mean[s] = float(e.mean())
         m_c = mean[seg].reshape(C, T)
         v_c = var[seg].reshape(C, T)
         pm = m_c.mean(0)
@@ -94,7 +119,7 @@ def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
         seg = slice(int(cstart[s]), int(cstart[s + 1]))
         pooled_mcse2[off[s]:off[s + 1]] = mc2[seg].reshape(C, T).sum(0) / (C * C)
     theta_mean = th.mean(axis=0).reshape(S, C, 5).mean(axis=1)
-    return dict(ess_h=ess_h, ess_theta=ess_th, elapsed=elapsed,
+    return dict(ess_h=ess_h, ess_h_mean=ess_h_mean, ess_theta=ess_th, elapsed=elapsed, n=n,
                 acceptance=float(out["accepted"].float().mean().item()),
                 mean=pooled_mean, var=pooled_var, mcse2=pooled_mcse2, theta_mean=theta_mean,
                 theta_trace=th)
@@ -109,8 +134,10 @@ def chains_for(data, C):
 
 
 def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True,
-            dtau_jitter=0.0, level=False, tune_shape=False):
+            dtau_jitter=0.0, level=False, tune_shape=False, log_mass=None):
     """One arm on one batch of series; returns measure() output plus dtau.
+    The mass comes from `net` (evaluated after the first half of warm-up) or,
+    for a reference arm, is the fixed per-site `log_mass` given.
     update_theta=False holds every chain at its series' generating theta (an
     exactness check of the h update alone: the h-conditional mixes in a few
     sweeps, so batch-means standard errors are reliable)."""
@@ -128,17 +155,24 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
                                          [(k, d) for d in dtau], n_sweeps=4, **tkw)
         shape = dict(sites_per_lane=S_, waves_per_tile=NW_)
     smp = api.RSVSampler(off, data["y"], data["log_rv"], h0, thetas, **kw, **shape)
-    dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 100, S, C,
+    dtau, sweep, _, theta_now = adapt(smp, k, dtau, 0, warm // 2, S, C,
                                       update_theta=update_theta)
-    log_m = None
-    if net is not None:
-        theta_hat = theta_now.mean(axis=0).reshape(S, C, 5).mean(axis=1)
-        x = net.features(off, data["y"], data["log_rv"], theta_hat)
-        log_m = net.log_mass(x)
+    lm_host, fallback = None, []
+    learned = net is not None or log_mass is not None
+    if learned:
+        if net is not None:
+            theta_hat = theta_now.mean(axis=0).reshape(S, C, 5).mean(axis=1)
+            x = net.features(off, data["y"], data["log_rv"], theta_hat)
+            lm_host, fallback = series_log_mass(net.log_mass(x).cpu().numpy(), off)
+        else:
+            lm_host, fallback = series_log_mass(log_mass, off)
         state = smp.h.to(torch.float64).cpu().numpy()
         th_now = smp.theta.cpu().numpy()
         smp.close()
-        lm_host = log_m.cpu().numpy()
+        # a mass m moves h by about dtau / sqrt(m) per step: start the second
+        # half of warm-up from dtau sqrt(median m) of each series
+        dtau = dtau * np.array([np.exp(0.5 * np.median(lm_host[off[s]:off[s + 1]]))
+                                for s in range(S)])
         if tune_shape:
             S_, NW_, _ = autotune.best_shape(off, data["y"], data["log_rv"], state, th_now,
                                              [(k, d) for d in dtau], n_sweeps=4,
@@ -146,10 +180,28 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
             shape = dict(sites_per_lane=S_, waves_per_tile=NW_)
         smp = api.RSVSampler(off, data["y"], data["log_rv"], state, th_now,
                              log_mass=lm_host, **kw, **shape)
-    dtau, sweep, _, _ = adapt(smp, k, dtau, sweep, warm // 100, S, C, update_theta=update_theta)
+    dtau, sweep, acc, _ = adapt(smp, k, dtau, sweep, warm // 2, S, C, update_theta=update_theta)
+    if learned and np.any(acc < 0.5):
+        # identity fallback for the series whose warm-up acceptance under the
+        # learned mass stayed below 0.5: they restart the second half of
+        # warm-up with m = 1 from their state at this point
+        low = np.flatnonzero(acc < 0.5)
+        for s in low:
+            dtau[s] = dtau[s] / np.exp(0.5 * np.median(lm_host[off[s]:off[s + 1]]))
+            lm_host[off[s]:off[s + 1]] = 0.0
+        fallback = sorted(set(fallback) | set(int(s) for s in low))
+        state = smp.h.to(torch.float64).cpu().numpy()
+        th_now = smp.theta.cpu().numpy()
+        smp.close()
+        smp = api.RSVSampler(off, data["y"], data["log_rv"], state, th_now,
+                             log_mass=lm_host, **kw, **shape)
+        dtau, sweep, acc, _ = adapt(smp, k, dtau, sweep, warm // 2, S, C,
+                                    update_theta=update_theta)
     res = measure(smp, k, dtau, sweep, n, bl, off, C, update_theta=update_theta)
     res["dtau"] = dtau
-    res["log_mass"] = None if log_m is None else log_m
+    res["warmup_acceptance"] = acc
+    res["log_mass"] = lm_host
+    res["fallback_series"] = fallback
     res["shape"] = shape
     smp.close()
     return res

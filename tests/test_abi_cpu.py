@@ -132,3 +132,19 @@ def test_static_workspace_limit_checked_on_the_host():
     assert b"static workspace" in api.lib().rsv_last_error()
     small = _pb([0, 1000], max_steps=20)
     assert api.rsv_hmc_workspace_bytes(small) < _lib.RSV_STATIC_WORKSPACE_BYTES
+
+
+def test_series_log_mass_falls_back_per_series():
+    """Host logic of the learned-mass pipeline: a series with any non-finite
+    network output takes the identity mass (ln m = 0) at every site; the
+    other series keep theirs."""
+    from paper_1603_08114_amd import learned_mass as LM
+    off = np.array([0, 4, 9, 12])
+    lm = np.arange(12, dtype=np.float32) / 10
+    lm[6] = np.nan
+    lm[11] = np.inf
+    out, bad = LM.series_log_mass(lm, off)
+    assert bad == [1, 2]
+    assert np.array_equal(out[:4], lm[:4])
+    assert np.all(out[4:] == 0.0)
+    assert np.isnan(lm[6])  # the input is not modified
