@@ -41,15 +41,6 @@ def simulate_rsv(T: int, theta: dict, seed: int):
     return y, log_rv, h
 
 
-def _ar1_fast(T, phi, mu, s_eta, eta):
-    # h_t - mu = phi (h_{t-1} - mu) + s_eta eta_t, vectorised by blocks.
-    a = np.empty(T)
-    a[0] = eta[0] * s_eta / np.sqrt(1.0 - phi * phi)
-    for t in range(1, T):
-        a[t] = phi * a[t - 1] + s_eta * eta[t]
-    return a + mu
-
-
 def simulate_rsv_long(T: int, theta: dict, seed: int):
     """Same law as simulate_rsv for long T, with the AR(1) recursion run by
     scipy's linear filter.  Returns (y, log_rv, h_true)."""
