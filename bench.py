@@ -58,16 +58,18 @@ def parse():
                          "workload's default (off for long and small, on for batched and mass)")
     ap.add_argument("--dtau-jitter", type=float, default=-1.0,
                     help="step-size jitter j (dtau * U[1-j, 1+j] per trajectory); -1 = the "
-                         "workload's default (0 for the fixed-dtau long and small workloads, "
-                         "0.5 for batched, mass and the precision study's chains)")
+                         "workload's default (0, the paper's fixed dtau; the batched and mass "
+                         "workloads report jitter 0.5 with the level move beside their value)")
     ap.add_argument("--cpu-sweeps", type=int, default=2,
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="long workload only: skip the single-series and batched min-ESS/s legs")
-    ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "precision"],
+    ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "sv", "precision"],
                     default="long",
                     help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
-                         "batched: 512 series x 4 chains, FP32-mixed")
+                         "batched: 512 series x 4 chains, FP32-mixed; mass: learned diagonal "
+                         "mass (RSV, with the SV model's arms beside); sv: the learned-mass "
+                         "study on the plain SV model; precision: FP32-mixed vs FP64")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (for counter calibration)")
     ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE",
@@ -340,21 +342,24 @@ def batched_data(S_=512, C_=4):
 
 
 def batched_arm(data, k, jit, level, omelyan=False, shape=None, n=2000, bl=40,
-                precision=None):
-    """Warm-up with dtau adapted per series to ~0.8 acceptance (10 windows of 50
-    sweeps), then n measured sweeps with batch means accumulated on the
-    device; min over {h_t} and theta of the ESS of each series (its chains
-    summed), per second of the measured sweeps.  shape None = autotuned."""
+                precision=None, terms=None):
+    """Warm-up of 500 sweeps with dtau adapted per series to acceptance 0.8
+    (stochastic approximation on ln dtau, windows of 25 sweeps), then n
+    measured sweeps with batch means accumulated on the device; min over
+    {h_t} and theta of the ESS of each series (its chains summed), per second
+    of the measured sweeps.  shape None = autotuned."""
     import torch
-    from paper_1603_08114_amd import api, autotune, diagnostics
-    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN
+    from paper_1603_08114_amd import api, autotune, diagnostics, learned_mass as LM
+    from paper_1603_08114_amd._lib import (RSV_F32_MIXED, RSV_FLAG_LEVEL_MOVE, RSV_FLAG_OMELYAN,
+                                           RSV_TERMS_RSV)
+    terms = RSV_TERMS_RSV if terms is None else terms
     precision = RSV_F32_MIXED if precision is None else precision
     off, C_ = data["offsets"], data["C"]
     Ts = np.diff(off)
     S_ = Ts.size
     k_ = k // 2 if omelyan else k
     dtau = (2.0 if omelyan else 1.0) * 0.05 * (1000.0 / Ts) ** 0.25
-    kw = dict(chains_per_series=C_, precision=precision, dtau_jitter=jit,
+    kw = dict(chains_per_series=C_, precision=precision, dtau_jitter=jit, terms=terms,
               flags=(RSV_FLAG_LEVEL_MOVE if level else 0) | (RSV_FLAG_OMELYAN if omelyan else 0))
     table = None
     if shape is None:
@@ -367,14 +372,7 @@ def batched_arm(data, k, jit, level, omelyan=False, shape=None, n=2000, bl=40,
         S_t, NW_t = shape
     smp = api.RSVSampler(off, data["y"], data["log_rv"], data["h0"], data["theta0"], max_steps=k_,
                          seed=3, sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
-    sweep = 0
-    for _ in range(10):  # 10 windows of 50 warm-up sweeps
-        out = smp.sweep(sweep, 50, [(k_, d) for d in dtau], update_theta=True,
-                        record=("delta_h",))
-        sweep += 50
-        dh = out["delta_h"].cpu().numpy().reshape(50, S_, C_)
-        acc = np.minimum(1.0, np.exp(-np.nan_to_num(dh, nan=1e9))).mean(axis=(0, 2))
-        dtau = dtau * np.exp(1.5 * (acc - 0.8))
+    dtau, sweep, _, _ = LM.adapt(smp, k_, dtau, 0, 500, S_, C_, update_theta=True)
     lf = [(k_, d) for d in dtau]
     smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
     sweep += 1
@@ -495,92 +493,174 @@ def batched_cpu_baseline(data, k, dtau, jit, level, n_sweeps=25):
             "seconds": dt, "nproc": nproc, "cpu_model": model}
 
 
-def run_mass(args):
-    """Learned diagonal mass: train on identity-FP64 chains of 256 series
-    (T ~ U{500..8000}, seed 4), evaluate on 1024 held-out series
-    (T ~ U{1000..16000}, seed 5), 4 chains each, k = 30, against identity
-    mass, same warm-up (500 sweeps, dtau adapted per series) and 1000 measured
-    sweeps per arm.  value = median over series of min-ESS/s, learned mass
-    with FP32-mixed leapfrog; the other arms are reported beside it."""
+def mass_oracle_leg(held, net_log_m, k, n_series=8, C=16, n_burn=100, n=300, terms=None,
+                    label="learned mass FP32"):
+    """cpu_baseline leg of the mass workloads: C oracle chains per series on
+    the host (one per thread) beside C GPU chains (learned mass, FP32-mixed),
+    for the n_series held-out series closest to the median length; theta
+    updated, dtau = 0.05 (1000 / T)^(1/4) sqrt(median m), 100 burn-in and
+    300 kept sweeps from the simulated path and the generating theta.  The
+    oracle chains are timed (the CPU baseline) and their posterior moments
+    are the reference of the moment rule."""
+    import oracle
+    from oracle.chains import chain_moments
+    from paper_1603_08114_amd import moments as M
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_TERMS_RSV
+    terms = RSV_TERMS_RSV if terms is None else terms
+    off = held["offsets"]
+    Ts = np.diff(off)
+    pick = np.sort(np.argsort(np.abs(Ts - np.median(Ts)))[:n_series])
+    sub_off = np.concatenate([[0], np.cumsum(Ts[pick])])
+    cat = lambda a: np.concatenate([a[off[s]:off[s + 1]] for s in pick])
+    y, lr, lm = cat(held["y"]), cat(held["log_rv"]), cat(net_log_m).astype(np.float32)
+    h0s = [held["h_true"][off[s]:off[s + 1]] for s in pick]
+    th = [held["thetas"][s] for s in pick]
+    dts = np.array([0.05 * (1000.0 / Ts[s]) ** 0.25 *
+                    np.exp(0.5 * np.median(lm[sub_off[i]:sub_off[i + 1]]))
+                    for i, s in enumerate(pick)])
+    gpu = M.gpu_chain_moments(sub_off, y, lr, h0s, th, C, k, dts, n_burn, n, RSV_F32_MIXED, 303,
+                              log_mass=lm, terms=terms)
+    ref = chain_moments(sub_off, y, lr, h0s, th, C, k, dts, n_burn, n, 404,
+                        terms=oracle.TERMS_RSV if terms == RSV_TERMS_RSV else terms,
+                        log_m=lm.astype(np.float64))
+    ok, report = M.compare(gpu, ref)
+    print(f"[mass] moments {label} vs oracle: ok={ok} {report}", file=sys.stderr, flush=True)
+    cores, nproc, model = host_cpu()
+    baseline = {"value": ref["site_updates"] / ref["seconds"], "unit": "site-updates/s",
+                "cores": ref["threads"], "kind": "oracle",
+                "sample": f"{C} oracle chains x {n_series} held-out series (T {int(Ts[pick].min())}"
+                          f"..{int(Ts[pick].max())}), {n_burn + n} sweeps each, learned mass, one "
+                          f"chain per thread, FP64 serial C per chain",
+                "seconds": ref["seconds"], "nproc": nproc, "cpu_model": model}
+    moments = {"rule": "per family: fraction of p < 0.0027 <= 0.0027 + 3 binomial SE, "
+                       "min p >= 0.01/N (Welch t over 16 chains per side)",
+               "pass": ok, "gpu_acceptance": gpu["acceptance"], **report,
+               "series": int(n_series), "chains_per_side": C, "sweeps": f"{n_burn}+{n}"}
+    return baseline, moments
+
+
+def mass_study(args, terms):
+    """Learned diagonal mass on batched series of one model (terms): train on
+    plain FP64 chains of 256 series (T ~ U{500..8000}, seed 4), evaluate on
+    1024 held-out series (T ~ U{1000..16000}, seed 5), 4 chains each, k = 30,
+    500 warm-up sweeps (dtau adapted per series to acceptance 0.8) and 1000
+    measured sweeps per arm.  Arms under the paper's sampler (fixed dtau per
+    trajectory, Gibbs theta): identity FP64, learned FP32-mixed, identity
+    FP32-mixed, learned FP64; beside them the two FP32 arms with the
+    extensions (step jitter 0.5 and the level move)."""
     import torch
     import synth
     from paper_1603_08114_amd import learned_mass as LM
-    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64, RSV_TERM_RETURN
+    sv = terms == RSV_TERM_RETURN
+    tag = "sv" if sv else "rsv"
     C, k = 4, 30
     n_train, n_held = (64, 128) if args.steps < 200 else (256, 1024)
     train = synth.make_batch(n_train, 500, 8000, seed=4)
     held = synth.make_batch(n_held, 1000, 16000, seed=5)
-    print(f"[mass] training targets from {n_train} series", file=sys.stderr, flush=True)
-    jit = jitter_of(args, 0.5)
-    level = level_of(args, True)
-    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000, dtau_jitter=jit, level=level)
+    if sv:  # the SV model has no realised-variance series: the network sees zeros there
+        train["log_rv"] = np.zeros_like(train["log_rv"])
+        held["log_rv"] = np.zeros_like(held["log_rv"])
+    jit, level = jitter_of(args, 0.0), level_of(args, False)
+    print(f"[{tag}] training targets from {n_train} series", file=sys.stderr, flush=True)
+    tr = LM.training_targets(train, C=C, k=k, warm=500, n=2000, dtau_jitter=jit, level=level,
+                             terms=terms)
     target = -torch.log(torch.clamp(tr["var"], min=1e-12))
     net, hist, r2 = LM.train_network(train, target, tr["theta_mean"], epochs=30)
-    print(f"[mass] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, R^2 {r2:.3f}", file=sys.stderr,
-          flush=True)
-    arms = {"identity_f64": (RSV_F64, None), "learned_f32": (RSV_F32_MIXED, net),
-            "identity_f32": (RSV_F32_MIXED, None), "learned_f64": (RSV_F64, net)}
-    out = {}
-    res_arm = {}
-    for name, (prec, nt) in arms.items():
-        r = LM.run_arm(held, C, k, prec, nt, seed=5, warm=500, n=1000, bl=25, dtau_jitter=jit,
-                       level=level, tune_shape=True)
-        res_arm[name] = r
-        per = np.minimum(r["ess_h"], r["ess_theta"]) / r["elapsed"]
-        out[name] = {"median_min_ess_per_s": float(np.median(per)),
-                     "min_min_ess_per_s": float(per.min()),
-                     "median_ess_h_per_s": float(np.median(r["ess_h"] / r["elapsed"])),
-                     "median_ess_theta_per_s": float(np.median(r["ess_theta"] / r["elapsed"])),
-                     "seconds": r["elapsed"], "acceptance": r["acceptance"],
-                     "median_dtau": float(np.median(r["dtau"])), "tile_shape": r["shape"]}
-        print(f"[mass] {name}: {out[name]}", file=sys.stderr, flush=True)
-    # Exactness of the learned-mass FP32 h update: posterior means of h_t with
-    # theta held at each series' generating value, learned FP32 vs identity FP64.
-    # (With theta updated, h_t means inherit theta's slow mixing and short-batch
-    # standard errors are too small to compare them.)
-    fixed = {}
-    for name, (prec, nt, sd) in {"identity_f64": (RSV_F64, None, 6),
-                                 "learned_f32": (RSV_F32_MIXED, net, 7)}.items():
-        fixed[name] = LM.run_arm(held, C, k, prec, nt, seed=sd, warm=500, n=1000, bl=25,
-                                 update_theta=False, dtau_jitter=jit)
-    a, b = fixed["identity_f64"], fixed["learned_f32"]
-    z = ((b["mean"] - a["mean"]) / torch.sqrt(a["mcse2"] + b["mcse2"])).cpu().numpy()
-    z = z[np.isfinite(z)]
-    frac3 = float(np.mean(np.abs(z) > 3))
-    lim = 0.0027 + 3 * np.sqrt(0.0027 * 0.9973 / z.size)
-    print(f"[mass] fixed-theta h means: frac |z|>3 {frac3:.4f} (limit {lim:.4f})",
+    print(f"[{tag}] trained: loss {hist[0]:.4f} -> {hist[-1]:.4f}, R^2 {r2:.3f}",
           file=sys.stderr, flush=True)
-    gain = out["learned_f32"]["median_min_ess_per_s"] / out["identity_f64"]["median_min_ess_per_s"]
-    res = {"metric": METRIC, "value": out["learned_f32"]["median_min_ess_per_s"],
-           "unit": "min-ESS/s (median over series)", "n_gpus": 1, "steps": 1000, "warmup": 500,
-           "ms_per_step": out["learned_f32"]["seconds"] / 1000 * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed + bf16 network",
-           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
-           "config": {"workload": f"learned diagonal mass: train {n_train} series, evaluate "
-                                  f"{n_held} held-out series x 4 chains, k=30, dtau jitter {jit}"
-                                  + (", level move" if level else ""),
-                      "train_series": n_train, "held_out_series": n_held, "k": k,
-                      "dtau_jitter": jit, "level_move": bool(level)},
-           "arms": out, "gain_learned_f32_vs_identity_f64": gain,
+
+    def arm(prec, nt, jit_, level_, seed=5):
+        r = LM.run_arm(held, C, k, prec, nt, seed=seed, warm=500, n=1000, bl=25,
+                       dtau_jitter=jit_, level=level_, tune_shape=True, terms=terms)
+        per = np.minimum(r["ess_h"], r["ess_theta"]) / r["elapsed"]
+        return r, {"median_min_ess_per_s": float(np.median(per)),
+                   "min_min_ess_per_s": float(per.min()),
+                   "median_ess_h_per_s": float(np.median(r["ess_h"] / r["elapsed"])),
+                   "median_ess_theta_per_s": float(np.median(r["ess_theta"] / r["elapsed"])),
+                   "median_ess_h_mean_per_sweep": float(np.median(r["ess_h_mean"] / r["n"])),
+                   "seconds": r["elapsed"], "ms_per_sweep": r["elapsed"] / r["n"] * 1e3,
+                   "acceptance": r["acceptance"],
+                   "warmup_acceptance_range": [float(np.min(r["warmup_acceptance"])),
+                                               float(np.max(r["warmup_acceptance"]))],
+                   "median_dtau": float(np.median(r["dtau"])), "tile_shape": r["shape"],
+                   "fallback_series": len(r["fallback_series"])}
+
+    arms, runs = {}, {}
+    for name, (prec, nt) in {"identity_f64": (RSV_F64, None), "learned_f32": (RSV_F32_MIXED, net),
+                             "identity_f32": (RSV_F32_MIXED, None),
+                             "learned_f64": (RSV_F64, net)}.items():
+        runs[name], arms[name] = arm(prec, nt, jit, level)
+        print(f"[{tag}] {name}: {arms[name]}", file=sys.stderr, flush=True)
+    ext = {}
+    for name, nt in {"identity_f32": None, "learned_f32": net}.items():
+        _, ext[name] = arm(RSV_F32_MIXED, nt, 0.5, True)
+        print(f"[{tag}] extension jitter 0.5 + level move, {name}: {ext[name]}", file=sys.stderr,
+              flush=True)
+    m = lambda a: arms[a]["median_min_ess_per_s"]
+    out = {"arms_paper_sampler": arms, "arms_extension_jitter_0.5_level_move": ext,
+           "gain_learned_f32_vs_identity_f64": m("learned_f32") / m("identity_f64"),
+           "gain_learned_f32_vs_identity_f32": m("learned_f32") / m("identity_f32"),
+           "gain_learned_f64_vs_identity_f64": m("learned_f64") / m("identity_f64"),
            "training": {"loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "r2": r2},
-           "fixed_theta_h_means_learned_f32_vs_identity_f64": {
-               "frac_abs_z_gt_3": frac3, "frac_limit": float(lim),
-               "max_abs_z": float(np.abs(z).max()), "n_sites": int(z.size),
-               "ess_h_per_s": {n_: float(np.median(r_["ess_h"] / r_["elapsed"]))
-                               for n_, r_ in fixed.items()}}}
+           "train_series": n_train, "held_out_series": n_held}
+    if args.cpu_sweeps > 0:
+        x = net.features(held["offsets"], held["y"], held["log_rv"],
+                         synth.theta_array(held["thetas"]))
+        out["cpu_baseline"], out["moments_learned_f32_vs_oracle"] = mass_oracle_leg(
+            held, net.log_mass(x).cpu().numpy(), k, terms=terms,
+            label=f"{tag} learned mass FP32")
+    return out
+
+
+def run_mass(args, terms=None):
+    """Learned diagonal mass (RSV model; with terms = return only, the plain
+    SV model).  value = median over series of min-ESS/s of the learned-mass
+    FP32 arm under the paper's sampler; the other arms, the extension arms
+    and the posterior-moment check against oracle chains beside it.  The RSV
+    line also carries the SV study's arms."""
+    from paper_1603_08114_amd._lib import RSV_TERM_RETURN, RSV_TERMS_RSV
+    terms = RSV_TERMS_RSV if terms is None else terms
+    sv = terms == RSV_TERM_RETURN
+    st = mass_study(args, terms)
+    a = st["arms_paper_sampler"]["learned_f32"]
+    model = "SV (eq. (2) dropped)" if sv else "RSV"
+    res = {"metric": METRIC, "value": a["median_min_ess_per_s"],
+           "unit": "min-ESS/s (median over series)", "n_gpus": 1, "steps": 1000, "warmup": 500,
+           "ms_per_step": a["ms_per_sweep"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32-mixed + bf16 network",
+           "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+           "config": {"workload": f"learned diagonal mass, {model}: train {st['train_series']} "
+                                  f"series, evaluate {st['held_out_series']} held-out series x 4 "
+                                  "chains, k=30, paper's sampler",
+                      "model": model, "train_series": st["train_series"],
+                      "held_out_series": st["held_out_series"], "k": 30}}
+    res.update({k_: v for k_, v in st.items() if k_ not in ("train_series", "held_out_series")})
+    if not sv:
+        sv_st = mass_study(args, RSV_TERM_RETURN)
+        res["sv_model"] = {k_: v for k_, v in sv_st.items() if k_ != "cpu_baseline"}
     return res
 
 
+def run_sv(args):
+    """The learned-mass study on the plain SV model (the return term only):
+    the identity arms are plain SV HMC under the paper's sampler."""
+    from paper_1603_08114_amd._lib import RSV_TERM_RETURN
+    return run_mass(args, terms=RSV_TERM_RETURN)
+
+
 def run_precision(args):
-    """FP32-mixed leapfrog against FP64 on T = 2^22 (theta of the single-series
-    workload, seed 2, k = 50): every FP32 trajectory has an FP64 shadow
-    trajectory from the identical h0, momenta and ln u; then the posterior
-    means of h_t and theta of an FP32 chain against an FP64 chain (batch
-    means, MCSE units).  value = median |dH_FP32 - dH_FP64|."""
+    """FP32-mixed leapfrog against FP64.  (1) On T = 2^22 (theta of the
+    single-series workload, seed 2, k = 50): every FP32 trajectory has an FP64
+    shadow trajectory from the identical h0, momenta and ln u; value = median
+    |dH_FP32 - dH_FP64|.  (2) On T = 2^16 (same theta, seed 2): 16 FP32-mixed
+    and 16 FP64 GPU chains against 16 oracle chains (the cpu_baseline leg),
+    100 burn-in + 300 sweeps with theta updated, posterior means and
+    variances of every h_t and of theta under the moment rule."""
     import torch
     import synth
-    from paper_1603_08114_amd import api, diagnostics
-    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64, RSV_FLAG_LEVEL_MOVE
+    from paper_1603_08114_amd import api
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
     T, k = args.T, args.k
     n = max(args.steps, 50)
     theta = dict(synth.THETA_STAR)
@@ -592,7 +672,7 @@ def run_precision(args):
     dtau = args.dtau if args.dtau > 0 else tune_dtau(s64, k, T, 0)[0]
     lf = (k, dtau)
     s32.sweep(0, 20, lf, update_theta=True, record=())
-    dA, dB, accA, accB, lus = [], [], [], [], []
+    dA, dB, accA, accB = [], [], [], []
     for i in range(n):
         sweep = 1000 + i
         s64.h.copy_(s32.h.to(torch.float64))
@@ -603,33 +683,10 @@ def run_precision(args):
         db, ab = s64.trajectory(sweep, lf, p0=p0, log_u=[lu])
         s32.theta_update(sweep, want_stats=False)
         dA.append(da.item()); dB.append(db.item()); accA.append(aa.item()); accB.append(ab.item())
-        lus.append(lu)
+    s32.close()
+    s64.close()
     dA, dB = np.array(dA), np.array(dB)
     err = np.abs(dA - dB)
-    # independent FP32 and FP64 chains: posterior means of h_t in MCSE units,
-    # theta held at its generating value (the h-conditional mixes in a few
-    # sweeps, so batch-means standard errors are reliable); then theta-updating
-    # chains for the theta means (Geyer standard errors: indicative only, theta
-    # mixes over hundreds of sweeps).
-    n_chain, bl = 10 * n, n // 5
-    stats = []
-    for upd in (False, True):
-        for prec, sd in ((RSV_F32_MIXED, 1), (RSV_F64, 2)):
-            smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k,
-                                 seed=args.seed + sd + (10 if upd else 0), precision=prec,
-                                 dtau_jitter=jitter_of(args, 0.5),
-                                 flags=RSV_FLAG_LEVEL_MOVE if level_of(args, True) else 0)
-            smp.sweep(0, 200, lf, update_theta=upd, record=())
-            o = smp.sweep(200, n_chain, lf, update_theta=upd, record=("theta",), batch_len=bl)
-            bm = o["h_batch_sum"] / bl
-            nb = bm.shape[0]
-            th = o["theta"][:, 0].cpu().numpy()
-            stats.append((bm.mean(0), bm.var(0) / nb, th.mean(0),
-                          th.var(0) / diagnostics.ess_geyer(th) if upd else None))
-            smp.close()
-    z = ((stats[0][0] - stats[1][0]) / torch.sqrt(stats[0][1] + stats[1][1])).cpu().numpy()
-    zt = (stats[2][2] - stats[3][2]) / np.sqrt(stats[2][3] + stats[3][3])
-    lim = 0.0027 + 3 * np.sqrt(0.0027 * 0.9973 / z.size)
     res = {"metric": METRIC, "value": float(np.median(err)), "unit": "|dH_FP32 - dH_FP64| (median)",
            "n_gpus": 1, "steps": n, "warmup": 20, "ms_per_step": None, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32-mixed vs f64",
@@ -639,13 +696,41 @@ def run_precision(args):
            "dH_abs_error": {"median": float(np.median(err)), "p99": float(np.quantile(err, 0.99)),
                             "max": float(err.max()), "median_abs_dH": float(np.median(np.abs(dB)))},
            "decision_disagreements": int(np.sum(np.array(accA) != np.array(accB))),
-           "trajectories": n,
-           "moments_fp32_vs_fp64_chains": {"sweeps": n_chain, "h_theta": "fixed at generating value",
-                                           "h_frac_abs_z_gt_3": float(np.mean(np.abs(z) > 3)),
-                                           "h_frac_limit": float(lim), "h_max_abs_z": float(np.abs(z).max()),
-                                           "theta_z_indicative": dict(zip(("phi", "mu", "xi", "sig2_eta", "sig2_u"),
-                                                               map(float, zt)))}}
+           "trajectories": n}
+    if args.cpu_sweeps > 0:
+        res["cpu_baseline"], res["moments_vs_oracle_T65536"] = precision_oracle_leg(args)
     return res
+
+
+def precision_oracle_leg(args, T=1 << 16, k=50, C=16, n_burn=100, n=300):
+    """cpu_baseline leg of the precision study: C oracle chains on the host
+    (one per thread), timed, and C FP32-mixed and C FP64 GPU chains from the
+    same start compared with them under the moment rule."""
+    from oracle.chains import chain_moments
+    import synth
+    from paper_1603_08114_amd import moments as M
+    from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64
+    th = dict(synth.THETA_STAR)
+    y, lr, h_true = synth.simulate_rsv_long(T, th, args.seed)
+    dt = 0.05 * (1000.0 / T) ** 0.25
+    off = np.array([0, T])
+    ref = chain_moments(off, y, lr, [h_true], [th], C, k, [dt], n_burn, n, 202)
+    out = {"rule": "per family: fraction of p < 0.0027 <= 0.0027 + 3 binomial SE, "
+                   "min p >= 0.01/N (Welch t over 16 chains per side)",
+           "T": T, "k": k, "dtau": dt, "chains_per_side": C, "sweeps": f"{n_burn}+{n}"}
+    for name, prec, seed in (("f32_mixed", RSV_F32_MIXED, 101), ("f64", RSV_F64, 103)):
+        gpu = M.gpu_chain_moments(off, y, lr, [h_true], [th], C, k, [dt], n_burn, n, prec, seed)
+        ok, report = M.compare(gpu, ref)
+        print(f"[precision] moments {name} vs oracle: ok={ok} {report}", file=sys.stderr,
+              flush=True)
+        out[name] = {"pass": ok, "gpu_acceptance": gpu["acceptance"], **report}
+    cores, nproc, model = host_cpu()
+    baseline = {"value": ref["site_updates"] / ref["seconds"], "unit": "site-updates/s",
+                "cores": ref["threads"], "kind": "oracle",
+                "sample": f"{C} oracle chains of T={T}, k={k}, {n_burn + n} sweeps each, one "
+                          f"chain per thread, FP64 serial C per chain",
+                "seconds": ref["seconds"], "nproc": nproc, "cpu_model": model}
+    return baseline, out
 
 
 def calibrate_copy():
@@ -674,7 +759,7 @@ def main():
         return
     if args.workload != "long":
         res = {"small": run_small, "batched": run_batched, "mass": run_mass,
-               "precision": run_precision}[args.workload](args)
+               "sv": run_sv, "precision": run_precision}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     import numpy as np

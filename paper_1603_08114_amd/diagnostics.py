@@ -91,7 +91,10 @@ def spread_summary(per_chain) -> tuple:
 
 def welch_p(per_chain_a, per_chain_b):
     """Two-sided Welch-t p-values (and z) for equal grand means of a statistic
-    per quantity, from per-chain values (k_a, d) and (k_b, d)."""
+    per quantity, from per-chain values (k_a, d) and (k_b, d).  A quantity
+    that no chain of either side moves (a parameter held fixed) has no
+    spread: equal values give z = 0, p = 1; different values z = +-inf,
+    p = 0."""
     from scipy import stats
     ma, sa, ka = spread_summary(per_chain_a)
     mb, sb, kb = spread_summary(per_chain_b)
@@ -100,6 +103,10 @@ def welch_p(per_chain_a, per_chain_b):
     with np.errstate(divide="ignore", invalid="ignore"):
         z = (ma - mb) / se
         df = (va + vb) ** 2 / (va * va / (ka - 1) + vb * vb / (kb - 1))
+    a = np.asarray(per_chain_a, dtype=np.float64)
+    b = np.asarray(per_chain_b, dtype=np.float64)
+    fixed = (np.ptp(a, axis=0) == 0.0) & (np.ptp(b, axis=0) == 0.0)
+    z = np.where(fixed, np.where(a[0] == b[0], 0.0, np.sign(a[0] - b[0]) * np.inf), z)
     p = 2.0 * stats.t.sf(np.abs(z), np.where(np.isfinite(df), df, ka + kb - 2))
     return z, p
 

@@ -26,7 +26,7 @@ import numpy as np
 import torch
 
 from . import api, autotune, diagnostics, mass
-from ._lib import RSV_F64, RSV_FLAG_LEVEL_MOVE
+from ._lib import RSV_F64, RSV_FLAG_LEVEL_MOVE, RSV_TERMS_RSV
 
 
 def _series_view(off, C):
@@ -108,7 +108,9 @@ def measure(smp, lf_k, dtau, sweep, n, bl, off, C, update_theta=True):
         pooled_var[off[s]:off[s + 1]] = (v_c + m_c * m_c).mean(0) - pm * pm
         if update_theta:
             e_th = sum(diagnostics.ess_geyer(th[:, s * C + j, :]) for j in range(C))
-            ess_th[s] = float(np.min(e_th))
+            # components the model holds fixed (xi, sigma_u^2 without the RV
+            # term) have no ESS and are left out
+            ess_th[s] = float(np.nanmin(e_th))
         else:
             ess_th[s] = np.inf
     # MCSE^2 of the pooled (over chains) posterior mean of each data site
@@ -134,7 +136,7 @@ def chains_for(data, C):
 
 
 def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, update_theta=True,
-            dtau_jitter=0.0, level=False, tune_shape=False, log_mass=None):
+            dtau_jitter=0.0, level=False, tune_shape=False, log_mass=None, terms=RSV_TERMS_RSV):
     """One arm on one batch of series; returns measure() output plus dtau.
     The mass comes from `net` (evaluated after the first half of warm-up) or,
     for a reference arm, is the fixed per-site `log_mass` given.
@@ -145,7 +147,7 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
     S = len(off) - 1
     Ts = np.diff(off)
     h0, thetas = chains_for(data, C)
-    kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed,
+    kw = dict(chains_per_series=C, precision=precision, max_steps=k, seed=seed, terms=terms,
               dtau_jitter=dtau_jitter, flags=RSV_FLAG_LEVEL_MOVE if level else 0)
     dtau = 0.05 * (1000.0 / Ts) ** 0.25
     shape = {}
@@ -207,10 +209,11 @@ def run_arm(data, C, k, precision, net=None, seed=0, warm=500, n=1000, bl=25, up
     return res
 
 
-def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0, dtau_jitter=0.0, level=False):
+def training_targets(data, C=4, k=30, warm=500, n=2000, seed=0, dtau_jitter=0.0, level=False,
+                     terms=RSV_TERMS_RSV):
     """Pooled per-site posterior mean and variance from identity FP64 chains."""
     res = run_arm(data, C, k, RSV_F64, None, seed=seed, warm=warm, n=n, bl=40,
-                  dtau_jitter=dtau_jitter, level=level)
+                  dtau_jitter=dtau_jitter, level=level, terms=terms)
     return res
 
 
@@ -231,6 +234,9 @@ def feature_stats(data, theta_series):
     mt = (th * w[:, None]).sum(0)
     mean[22:] = mt
     std[22:] = np.sqrt(((th - mt) ** 2 * w[:, None]).sum(0)) + 1e-12
+    # an input that is constant over the training set (the realised-variance
+    # window of the SV model) is centred and left unscaled
+    std[std == 0.0] = 1.0
     return mean, std
 
 

@@ -72,3 +72,15 @@ def test_welch_p_matches_scipy_ttest():
     _, p = D.welch_p(a, b)
     ref = stats.ttest_ind(a, b, axis=0, equal_var=False).pvalue
     np.testing.assert_allclose(p, ref, rtol=1e-10)
+
+
+def test_welch_p_fixed_quantity():
+    """A quantity constant over every chain of both sides: equal -> p = 1,
+    different -> p = 0; the other quantities are unaffected."""
+    rng = np.random.default_rng(3)
+    a = np.column_stack([rng.standard_normal(16), np.full(16, 0.2), np.full(16, 0.1)])
+    b = np.column_stack([rng.standard_normal(16), np.full(16, 0.2), np.full(16, 0.3)])
+    z, p = D.welch_p(a, b)
+    assert np.isfinite(z[0]) and 0.0 < p[0] <= 1.0
+    assert z[1] == 0.0 and p[1] == 1.0
+    assert np.isinf(z[2]) and p[2] == 0.0

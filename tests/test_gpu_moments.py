@@ -3,135 +3,36 @@
 Exactness of the FP32-mixed leapfrog (precision study) and of the FP32
 learned-mass path (a diagonal mass changes only the kinetic term of H,
 Sec. 3, and the Metropolis test is unchanged) means their chains sample the
-same posterior as FP64 oracle chains of the same sampler.  Each side runs 16 independent chains from the same
-start; means and variances of every h_t and of the five theta components are
+same posterior as FP64 oracle chains of the same sampler.  Each side runs 16
+independent chains from the same start; means and variances of every h_t and of the five theta components are
 compared with standard errors from the chain-to-chain spread (Welch t).
 
 Rule, fixed before running (paper_1603_08114_amd.diagnostics.moment_rule):
 over the N sites, the fraction of p-values below 0.0027 may exceed 0.0027 by
 at most three binomial standard errors, and the smallest p-value must be at
-least 0.01 / N; each theta component (means and variances) needs p >=
-0.01 / 5.
+least 0.01 / N; every theta component compared (means and variances, five
+per series) needs p >= 0.01 / (their count).
 """
-import os
-from concurrent.futures import ThreadPoolExecutor
-
 import numpy as np
 import pytest
 
-import oracle
 import synth
+from oracle.chains import chain_moments
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
-from paper_1603_08114_amd import api, diagnostics as D  # noqa: E402
+from paper_1603_08114_amd import moments as M  # noqa: E402
 from paper_1603_08114_amd._lib import RSV_F32_MIXED, RSV_F64  # noqa: E402
 
 CHAINS = 16
-KEYS = oracle.THETA_KEYS
-
-
-def _cores():
-    try:
-        return max(1, min(16, len(os.sched_getaffinity(0))))
-    except AttributeError:
-        return 4
-
-
-def gpu_moments(off, y, lr, h0s, thetas, C, k, dts, n_burn, n, precision, seed, log_mass=None,
-                update_theta=True):
-    """Per-chain means and variances of h_t (chains, sites of the series
-    concatenated) and of theta (chains, 5) over n sweeps after n_burn."""
-    S = len(off) - 1
-    Ts = np.diff(off)
-    h0 = np.concatenate([np.tile(h0s[s], C) for s in range(S)])
-    th = [thetas[s] for s in range(S) for _ in range(C)]
-    smp = api.RSVSampler(off, y, lr, h0, th, chains_per_series=C, precision=precision,
-                         max_steps=k, seed=seed, log_mass=log_mass)
-    lf = [(k, d) for d in dts]
-    smp.sweep(0, n_burn, lf, update_theta=update_theta, record=())
-    bl = 20
-    out = smp.sweep(n_burn, n, lf, update_theta=update_theta, record=("theta", "accepted"),
-                    batch_len=bl)
-    total = out["h_batch_sum"].sum(0).cpu().numpy()
-    sq = out["h_sq_sum"].cpu().numpy()
-    thr = out["theta"].cpu().numpy()  # (n, chains, 5)
-    acc = float(out["accepted"].float().mean())
-    smp.close()
-    means, variances = [], []
-    for j in range(C):  # per chain: its sites of every series, in series order
-        m, v = [], []
-        for s in range(S):
-            a = C * int(off[s]) + j * int(Ts[s])
-            mu = total[a:a + Ts[s]] / n
-            m.append(mu)
-            v.append(sq[a:a + Ts[s]] / n - mu * mu)
-        means.append(np.concatenate(m))
-        variances.append(np.concatenate(v))
-    th_c = thr.reshape(n, S, C, 5).transpose(2, 1, 0, 3)  # (C, S, n, 5)
-    return (np.array(means), np.array(variances), th_c.mean(axis=2).reshape(C, -1),
-            th_c.var(axis=2).reshape(C, -1), acc)
-
-
-def oracle_moments(off, y, lr, h0s, thetas, C, k, dts, n_burn, n, seed, update_theta=True,
-                   seg=40, log_m=None):
-    """The same statistics from C oracle chains per series (FP64; identity
-    mass unless log_m is given), one chain per host thread."""
-    S = len(off) - 1
-
-    def one(job):
-        s, c = job
-        y2 = y[off[s]:off[s + 1]] ** 2
-        r = lr[off[s]:off[s + 1]]
-        kw = dict(seed=seed, chain=c, update_theta=update_theta,
-                  log_m=None if log_m is None else log_m[off[s]:off[s + 1]])
-        o = oracle.run(h0s[s], thetas[s], y2, r, k, dts[s], n_burn, **kw)
-        h, th = o["h"], o["theta"]
-        s1 = np.zeros(h.size)
-        s2 = np.zeros(h.size)
-        ths, done = [], 0
-        while done < n:
-            m = min(seg, n - done)
-            o = oracle.run(h, th, y2, r, k, dts[s], m, first_sweep=n_burn + done, keep_h=True,
-                           **kw)
-            s1 += o["h_trace"].sum(0)
-            s2 += (o["h_trace"] ** 2).sum(0)
-            ths.append(o["theta_trace"])
-            h, th = o["h"], o["theta"]
-            done += m
-        mu = s1 / n
-        tt = np.concatenate(ths)
-        return mu, s2 / n - mu * mu, tt.mean(0), tt.var(0)
-
-    jobs = [(s, c) for c in range(C) for s in range(S)]
-    with ThreadPoolExecutor(_cores()) as ex:
-        res = list(ex.map(one, jobs))
-    means = np.array([np.concatenate([res[c * S + s][0] for s in range(S)]) for c in range(C)])
-    variances = np.array([np.concatenate([res[c * S + s][1] for s in range(S)])
-                          for c in range(C)])
-    th_m = np.array([np.concatenate([res[c * S + s][2] for s in range(S)]) for c in range(C)])
-    th_v = np.array([np.concatenate([res[c * S + s][3] for s in range(S)]) for c in range(C)])
-    return means, variances, th_m, th_v
 
 
 def check(gpu, ref, label, with_theta=True):
     """Apply the rule to means and variances of h and theta; print the summary."""
-    report = {}
-    ok_all = True
-    for name, a, b in (("h_mean", gpu[0], ref[0]), ("h_var", gpu[1], ref[1])):
-        z, p = D.welch_p(a, b)
-        ok, summary = D.moment_rule(p)
-        summary["max_abs_z"] = float(np.nanmax(np.abs(z)))
-        report[name] = summary
-        ok_all = ok_all and ok
-    if with_theta:
-        for name, a, b in (("theta_mean", gpu[2], ref[2]), ("theta_var", gpu[3], ref[3])):
-            z, p = D.welch_p(a, b)
-            report[name] = {"z": [round(float(v), 2) for v in z], "min_p": float(np.min(p))}
-            ok_all = ok_all and bool(np.min(p) >= 0.01 / p.size)
-    print(f"{label}: {report}")
-    return ok_all
+    ok, report = M.compare(gpu, ref, with_theta=with_theta)
+    print(f"{label}: acceptance {gpu['acceptance']:.3f} {report}")
+    return ok
 
 
 @pytest.mark.parametrize("precision", [RSV_F32_MIXED, RSV_F64])
@@ -145,9 +46,10 @@ def test_precision_chains_match_oracle_moments(precision):
     y, lr, h_true = synth.simulate_rsv_long(T, th, 2)
     dt = 0.05 * (1000.0 / T) ** 0.25
     off = np.array([0, T])
-    gpu = gpu_moments(off, y, lr, [h_true], [th], CHAINS, k, [dt], n_burn, n, precision, 101)
-    ref = oracle_moments(off, y, lr, [h_true], [th], CHAINS, k, [dt], n_burn, n, 202)
-    assert gpu[4] > 0.5
+    gpu = M.gpu_chain_moments(off, y, lr, [h_true], [th], CHAINS, k, [dt], n_burn, n, precision,
+                              101)
+    ref = chain_moments(off, y, lr, [h_true], [th], CHAINS, k, [dt], n_burn, n, 202)
+    assert gpu["acceptance"] > 0.5
     assert check(gpu, ref, f"T=2^16 precision {precision}")
 
 
@@ -187,11 +89,12 @@ def test_learned_mass_fp32_chains_match_oracle_moments(learned_mass_setup, updat
     dts = 0.05 * (1000.0 / Ts) ** 0.25 * np.array(
         [np.exp(0.5 * np.median(log_m[off[s]:off[s + 1]])) for s in range(len(Ts))])
     k, n_burn, n = 30, 100, 300
-    gpu = gpu_moments(off, held["y"], held["log_rv"], h0s, held["thetas"], CHAINS, k, dts,
-                      n_burn, n, RSV_F32_MIXED, 303, log_mass=log_m, update_theta=update_theta)
-    ref = oracle_moments(off, held["y"], held["log_rv"], h0s, held["thetas"], CHAINS, k, dts,
-                         n_burn, n, 404, update_theta=update_theta,
-                         log_m=log_m.astype(np.float64))
-    assert gpu[4] > 0.5
+    gpu = M.gpu_chain_moments(off, held["y"], held["log_rv"], h0s, held["thetas"], CHAINS, k,
+                              dts, n_burn, n, RSV_F32_MIXED, 303, log_mass=log_m,
+                              update_theta=update_theta)
+    ref = chain_moments(off, held["y"], held["log_rv"], h0s, held["thetas"], CHAINS, k, dts,
+                        n_burn, n, 404, update_theta=update_theta,
+                        log_m=log_m.astype(np.float64))
+    assert gpu["acceptance"] > 0.5
     assert check(gpu, ref, f"learned mass FP32 vs oracle, update_theta={update_theta}",
                  with_theta=update_theta)

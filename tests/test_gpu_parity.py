@@ -226,6 +226,21 @@ def test_sweep_with_level_move_matches_oracle(terms):
         assert np.mean(np.diff(ref["theta_trace"][:, 1]) != 0) > 0.9
 
 
+def test_sv_model_sweeps_match_oracle():
+    """The plain SV model (eq. (2) dropped: the return term only) under the
+    paper's sampler -- fixed dtau, no level move -- on ragged series over
+    several tiles, two chains each: accept sequence, dH, theta and h of every
+    sweep against the oracle's chain; xi and sigma_u^2 stay at their start."""
+    Ts, C, k, dt, n = [700, 2600], 2, 20, 0.04, 40
+    refs = sweep_parity(Ts, C, k, dt, n, 30, thetas=synth.draw_batch_thetas(len(Ts), 12),
+                        terms=1)
+    for ref in refs:
+        tr = ref["theta_trace"]
+        assert np.all(tr[:, 2] == tr[0, 2]) and np.all(tr[:, 4] == tr[0, 4])
+        assert np.mean(np.diff(tr[:, 0]) != 0) > 0.2  # phi moves (Metropolis step)
+        assert ref["accepted"].mean() > 0.5
+
+
 def test_theta_update_with_level_move_matches_oracle():
     from paper_1603_08114_amd._lib import RSV_FLAG_LEVEL_MOVE
     Ts, C = [1500, 5000], 2
@@ -357,12 +372,15 @@ def test_sweep_is_deterministic():
     assert torch.equal(oa["theta"], ob["theta"])
 
 
-def test_f32_mixed_trajectory_error_vs_f64():
+@pytest.mark.parametrize("terms", [3, 1])
+def test_f32_mixed_trajectory_error_vs_f64(terms):
     """FP32 leapfrog, FP64 dH: error against the FP64 oracle on identical
-    momenta.  Bound derived from FP32 rounding (u = 6e-8) accumulated over
-    k steps of a stable integrator on O(1) values."""
+    momenta, for the RSV model and the plain SV model (return term only).
+    Bound derived from FP32 rounding (u = 6e-8) accumulated over k steps of a
+    stable integrator on O(1) values."""
     k, dt = 20, 0.05
-    smp, offsets, ys, rs, h0, th = sampler([1000, 2500], 1, k=k, precision=RSV_F32_MIXED)
+    smp, offsets, ys, rs, h0, th = sampler([1000, 2500], 1, k=k, precision=RSV_F32_MIXED,
+                                           terms=terms)
     rng = np.random.default_rng(8)
     p0 = rng.standard_normal(smp.n_state)
     dh, acc = smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -50.0))
@@ -370,9 +388,9 @@ def test_f32_mixed_trajectory_error_vs_f64():
     h0_32 = h0.astype(np.float32).astype(np.float64)
     for c, (s, sl) in enumerate(chain_slices(offsets, 1)):
         h1, p1 = oracle.leapfrog(h0_32[sl], p0[sl].astype(np.float32).astype(np.float64),
-                                 ys[s] ** 2, rs[s], TH, k, dt)
+                                 ys[s] ** 2, rs[s], TH, k, dt, terms=terms)
         dH = oracle.delta_h(h0_32[sl], p0[sl].astype(np.float32).astype(np.float64), h1, p1,
-                            ys[s] ** 2, rs[s], TH)
+                            ys[s] ** 2, rs[s], TH, terms=terms)
         assert np.max(np.abs(h32[sl] - h1)) <= 2e-5
         assert abs(dh[c].item() - dH) <= 2e-3 * np.sqrt(sl.stop - sl.start) / 30
     assert bool(acc.all())
