@@ -64,12 +64,14 @@ def parse():
                     help="oracle sweeps timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="long workload only: skip the single-series and batched min-ESS/s legs")
-    ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "sv", "precision"],
+    ap.add_argument("--workload", choices=["long", "small", "batched", "mass", "sv", "precision",
+                                           "mlp"],
                     default="long",
                     help="long: one series T=2^22 (default); small: T=1000 min-ESS/s; "
                          "batched: 512 series x 4 chains, FP32-mixed; mass: learned diagonal "
                          "mass (RSV, with the SV model's arms beside); sv: the learned-mass "
-                         "study on the plain SV model; precision: FP32-mixed vs FP64")
+                         "study on the plain SV model; precision: FP32-mixed vs FP64; mlp: the "
+                         "mass network alone (BF16 MFMA)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (for counter calibration)")
     ap.add_argument("--summarize-counters", nargs=5, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE",
@@ -642,6 +644,71 @@ def run_mass(args, terms=None):
     return res
 
 
+MLP_FLOP_PER_SITE = 2 * (27 * 64 + 64 * 64 + 64)  # 27 -> 64 -> 64 -> 1, multiply-adds x 2
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_mlp(args):
+    """The learned-mass network alone: inference over the mass workload's
+    1024 held-out series (T ~ U{1000..16000}, seed 5; 8.7 M sites) and one
+    training epoch (batches of 8192 sites, gradient + Adam) over its 256
+    training series (T ~ U{500..8000}, seed 4), BF16 on the matrix cores.
+    value = inference rate in TFLOP/s at the algorithmic 11 776 FLOP per
+    site (the 27 real inputs; the kernel pads them to 32)."""
+    import torch
+    import synth
+    from paper_1603_08114_amd import mass
+    held = synth.make_batch(1024, 1000, 16000, seed=5)
+    train = synth.make_batch(256, 500, 8000, seed=4)
+    th_h = synth.theta_array(held["thetas"])
+    th_t = synth.theta_array(train["thetas"])
+    mean = np.zeros(27)
+    std = np.ones(27)
+    net = mass.MassNet(mass.init_params(0), mean, std)
+    xh = net.features(held["offsets"], held["y"], held["log_rv"], th_h)
+    xt = net.features(train["offsets"], train["y"], train["log_rv"], th_t)
+    tgt = torch.zeros(xt.shape[0], dtype=torch.float32, device=xt.device)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for _ in range(2):  # warm-up
+        net.forward(xh)
+    net.fit(xt, tgt, 1)
+    reps = max(3, min(args.steps, 20))
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(reps):
+        net.features(held["offsets"], held["y"], held["log_rv"], th_h)
+    ev[1].record(stream)
+    for _ in range(reps):
+        net.forward(xh)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_feat = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    t_fwd = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    ev[3].record(stream)
+    net.fit(xt, tgt, 1)
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    t_epoch = ev[3].elapsed_time(ev[4]) / 1e3
+    n_h, n_t = int(xh.shape[0]), int(xt.shape[0])
+    tf = MLP_FLOP_PER_SITE * n_h / t_fwd / 1e12
+    # training: forward + backward (input and weight gradients) = 3 x the forward products
+    tf_train = 3 * MLP_FLOP_PER_SITE * n_t / t_epoch / 1e12
+    return {"metric": METRIC, "value": tf, "unit": "TFLOP/s (BF16 MFMA inference, 11 776 FLOP/site)",
+            "n_gpus": 1, "steps": reps, "warmup": 2, "ms_per_step": t_fwd * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+            "config": {"workload": "learned-mass network 27-64-64-1: inference over 1024 held-out "
+                                   "series, one training epoch over 256 series",
+                       "inference_sites": n_h, "training_sites": n_t, "batch": 8192},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tf / BF16_PEAK_TFLOPS, "traffic": None},
+            "inference_ms": t_fwd * 1e3, "features_ms": t_feat * 1e3,
+            "inference_sites_per_s": n_h / t_fwd,
+            "training_epoch_ms": t_epoch * 1e3, "training_tflops": tf_train,
+            "training_sites_per_s": n_t / t_epoch}
+
+
 def run_sv(args):
     """The learned-mass study on the plain SV model (the return term only):
     the identity arms are plain SV HMC under the paper's sampler."""
@@ -759,7 +826,7 @@ def main():
         return
     if args.workload != "long":
         res = {"small": run_small, "batched": run_batched, "mass": run_mass,
-               "sv": run_sv, "precision": run_precision}[args.workload](args)
+               "sv": run_sv, "precision": run_precision, "mlp": run_mlp}[args.workload](args)
         print(json.dumps(res), flush=True)
         return
     import numpy as np
@@ -790,6 +857,21 @@ def main():
         print(f"[bench] tuned dtau={dtau:.6g} (pilot acceptance {acc_pilot:.3f})",
               file=sys.stderr, flush=True)
     lf = (k, dtau)
+    tune_table = None
+    if not args.sites_per_lane and not args.waves_per_tile:
+        # the tile shape by timing a few sweeps of every compiled shape
+        from paper_1603_08114_amd import autotune
+        S_t, NW_t, tune_table = autotune.best_shape([0, T], y, lr, h_true, theta, lf,
+                                                    precision=prec, n_sweeps=4,
+                                                    dtau_jitter=jit, seed=args.seed)
+        if (S_t, NW_t) != (S, NW):
+            smp.close()
+            smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=args.seed,
+                                 precision=prec, sites_per_lane=S_t, waves_per_tile=NW_t,
+                                 dtau_jitter=jit)
+            S, NW = S_t, NW_t
+        print(f"[bench] autotuned tile shape S={S} NW={NW}: {tune_table}", file=sys.stderr,
+              flush=True)
     smp.sweep(sweep, W, lf, update_theta=True, record=())
     sweep += W
     torch.cuda.synchronize()
@@ -862,7 +944,9 @@ def main():
         "config": {"workload": f"single-series RSV HMC sweep, T={T}, k={k}, "
                                f"{args.precision.upper()}, theta updated every sweep",
                    "T": T, "k": k, "dtau": dtau, "dtau_jitter": jit, "chains": 1,
-                   "sites_per_lane": S, "waves_per_tile": NW},
+                   "sites_per_lane": S, "waves_per_tile": NW,
+                   "tile_shape": "autotuned" if tune_table else "given"},
+        "autotune_seconds_per_sweep": tune_table,
         "roofline": roof,
         "acceptance": acc_rate,
         "traj_kernel_site_updates_per_s": traj_rate,
