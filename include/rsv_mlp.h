@@ -52,8 +52,9 @@ rsv_status rsv_mlp_features(int32_t n_series, const int64_t *offsets, const doub
                             const double *std, int64_t max_T, uint16_t *x, void *hip_stream);
 
 /* Forward pass for n rows of x: out[i] = network output (FP32).  If clip is
- * non-zero the output is clipped to [-5, 5] (the log mass used by the
- * sampler). */
+ * non-zero a finite output is clipped to [-5, 5] (the log mass used by the
+ * sampler); a non-finite one is written as it is, so that the caller's
+ * identity fallback sees it (rsv_hmc_init also takes m_t = 1 at such a site). */
 rsv_status rsv_mlp_forward(int64_t n, const uint16_t *x, const float *params, float *out,
                            int32_t clip, void *hip_stream);
 

@@ -137,5 +137,7 @@ def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def log_mass(p, X, bf16=True):
+    """The network output clipped to [-5, 5] where finite; a non-finite
+    output is returned as it is (the sampler's identity fallback handles it)."""
     out, _ = forward(p, X, bf16)
-    return np.clip(out, -LOG_MASS_CLIP, LOG_MASS_CLIP)
+    return np.where(np.isfinite(out), np.clip(out, -LOG_MASS_CLIP, LOG_MASS_CLIP), out)

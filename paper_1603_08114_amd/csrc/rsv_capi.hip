@@ -102,7 +102,7 @@ int32_t count_tiles(int32_t T, int S, int NW, int n_kicks) {
 struct Layout {
     size_t y2_d = 0, y2_f = 0, lrv_f = 0, h_prop = 0, tiles = 0, chains = 0, partials = 0,
            edge = 0, accept = 0, shift = 0, mass_sqrt = 0, acc = 0, counters = 0,
-           bins = 0, bin_chains = 0, bin_tiles = 0, total = 0;
+           bins = 0, bin_chains = 0, bin_tiles = 0, slices = 0, arrive = 0, total = 0;
     int32_t max_tiles = 0;
 };
 
@@ -194,6 +194,8 @@ rsv_status make_layout(const rsv_problem* pb, Layout* L) {
     L->bins = take(n_chains * sizeof(BinDesc));
     L->bin_chains = take(n_chains * sizeof(int32_t));
     L->bin_tiles = take(tiles * sizeof(int32_t));
+    L->slices = take((tiles / kSliceTiles + n_chains) * 2 * kNQ * sizeof(double));
+    L->arrive = take(n_chains * sizeof(uint32_t));
     L->total = off;
     L->max_tiles = static_cast<int32_t>(tiles);
     return RSV_OK;
@@ -231,6 +233,8 @@ struct rsv_ctx {
                                   // state's precision
     float* acc_f = nullptr;       // per state entry: FP32 batch sum, then batch sum of squares
     uint32_t* counters = nullptr;
+    double* slices = nullptr;     // split finalize: slice sums
+    uint32_t* arrive = nullptr;   // split finalize: per-chain arrival counts
     BinDesc* bins = nullptr;          // resident sweeps: bins of chains, one per block
     int32_t* bin_chains = nullptr;
     int32_t* bin_tiles = nullptr;
@@ -520,6 +524,8 @@ FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do
     f.counters = c->counters;
     f.level_move = level_moves(c) ? 1 : 0;
     f.shift = level_moves(c) ? c->shift : nullptr;
+    f.slices = c->slices;
+    f.arrive = c->arrive;
     return f;
 }
 
@@ -661,6 +667,8 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     c->bins = reinterpret_cast<BinDesc*>(c->ws + L.bins);
     c->bin_chains = reinterpret_cast<int32_t*>(c->ws + L.bin_chains);
     c->bin_tiles = reinterpret_cast<int32_t*>(c->ws + L.bin_tiles);
+    c->slices = reinterpret_cast<double*>(c->ws + L.slices);
+    c->arrive = reinterpret_cast<uint32_t*>(c->ws + L.arrive);
 
     auto bail = [&](rsv_status s) {
         delete c;
@@ -674,6 +682,7 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
     } while (0)
 
     RSV_HIP_INIT(hipMemsetAsync(c->counters, 0, kNumCounters * sizeof(uint32_t), c->stream));
+    RSV_HIP_INIT(hipMemsetAsync(c->arrive, 0, c->n_chains * sizeof(uint32_t), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->edge, 0, c->n_chains * kEdge * sizeof(double), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->accept, 0, c->n_chains * sizeof(int32_t), c->stream));
     RSV_HIP_INIT(hipMemsetAsync(c->shift, 0, c->n_chains * sizeof(double), c->stream));

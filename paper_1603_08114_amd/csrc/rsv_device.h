@@ -149,18 +149,25 @@ __device__ inline Comp comp_merge(Comp a, Comp b) {
     return r;
 }
 
-// Butterfly over the 64 lanes; every lane ends with the same total.
-__device__ inline Comp wave_comp_sum(Comp v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        Comp o;
-        o.s = __shfl_xor(v.s, off, kWave);
-        o.c = __shfl_xor(v.c, off, kWave);
-        // order the pair by lane so both partners compute the same merge
+// Compensated butterfly sums of N quantities over the 64 lanes (their merges
+// interleave), over the levels off = top, top/2, ..., 1; each pair is
+// ordered by lane so both partners compute the same merge, and with the full
+// butterfly (top = 32) every lane ends with the same totals.  With values
+// only in lanes [0, 2 top), the levels above top would merge every such lane
+// with zeros, which leaves it unchanged (up to the sign of an exact zero),
+// so lane 0 ends with the same totals as the full butterfly.
+template <int N>
+__device__ inline void wave_comp_sum_n(Comp (&v)[N], int top = kWave / 2) {
+    for (int off = top; off >= 1; off >>= 1) {
         const bool low = (threadIdx.x & off) == 0;
-        v = low ? comp_merge(v, o) : comp_merge(o, v);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            Comp o;
+            o.s = __shfl_xor(v[q].s, off, kWave);
+            o.c = __shfl_xor(v[q].c, off, kWave);
+            v[q] = low ? comp_merge(v[q], o) : comp_merge(o, v[q]);
+        }
     }
-    return v;
 }
 
 __device__ inline double wave_sum(double v) {

@@ -102,7 +102,14 @@ struct FinalizeArgs {
     uint32_t* counters;
     int32_t level_move;         // apply the level move before the Gibbs theta step
     double* shift;              // per chain pending level shift (with level_move)
+    double* slices;             // split finalize: compensated slice sums (kNQ pairs each)
+    uint32_t* arrive;           // split finalize: per chain, slices done (0 between launches)
 };
+
+// Split finalize: chains are reduced in slices of kSliceTiles tiles by one
+// block each; slice s of chain c is stored at index c + tile_begin / kSliceTiles
+// + s (disjoint across chains, at most tiles / kSliceTiles + n_chains).
+constexpr int kSliceTiles = 128;
 
 // Record the message returned by rsv_last_error() and return `code`.
 rsv_status set_error(rsv_status code, const char* where, const char* what);

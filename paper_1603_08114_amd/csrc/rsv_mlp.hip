@@ -166,7 +166,8 @@ __global__ __launch_bounds__(256) void k_mlp(int64_t n, const uint16_t* __restri
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t ri = row0 + 4 * q + j;
-                if (ri < n) out[ri] = clip ? fminf(fmaxf(o[j], -5.0f), 5.0f) : o[j];
+                // a non-finite output is passed on as it is, for the caller's fallback
+                if (ri < n) out[ri] = clip && isfinite(o[j]) ? fminf(fmaxf(o[j], -5.0f), 5.0f) : o[j];
             }
         }
         return;

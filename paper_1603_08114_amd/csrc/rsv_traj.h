@@ -910,6 +910,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Chain c's decision from its totals, by one lane: edge values, the pending
+// shift, finalize_decide, then the state selector and the shift.
+__device__ __forceinline__ void finalize_commit(const FinalizeArgs& A, const int c, const int T,
+                                                const double (&tot)[kNQ], ThetaDraws& draws) {
+    const double* ce = A.chain_edge + static_cast<int64_t>(c) * kEdge;
+    const double edge[kEdge] = {ce[0], ce[1], ce[2], ce[3]};
+    const double shift_in = A.shift ? A.shift[c] : 0.0;
+    const Decision d = finalize_decide(A, c, T, tot, edge, shift_in, draws);
+    if (d.accepted) A.state_sel[c] ^= 1;
+    if (A.shift) A.shift[c] = d.shift;
+}
+
 // Everything the finalize does for chain c, by NT threads (tid = 0..NT-1;
 // NT = 64: one wavefront, which may be one of several in its block) with
 // shared scratch passed in; returns in every thread.
@@ -940,24 +952,39 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
                 ve[q] = has_edge ? pe[q] : 0.0;
             }
             finalize_draws(A, c, cd.T, tid, NT, draws);
+            Comp acc[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                Comp acc{0.0, 0.0};
-                if (has) comp_add(acc, v[q]);
-                if (has_edge) comp_add(acc, ve[q]);
-                const Comp r = wave_comp_sum(acc);
-                if (lane == 0) part[0][q] = r;
+                acc[q] = Comp{0.0, 0.0};
+                if (has) comp_add(acc[q], v[q]);
+                if (has_edge) comp_add(acc[q], ve[q]);
+            }
+            // tiles in lanes [0, tile_count): the butterfly from the first
+            // level that pairs two of them
+            int top = 0;
+            if (cd.tile_count > 1) {
+                top = 1;
+                while (2 * top < cd.tile_count) top *= 2;
+            }
+            wave_comp_sum_n(acc, top);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) part[0][q] = acc[q];
             }
         } else {
             finalize_draws(A, c, cd.T, tid, NT, draws);
+            Comp acc[NQ];
             for (int q = 0; q < NQ; ++q) {
-                Comp acc{0.0, 0.0};
+                acc[q] = Comp{0.0, 0.0};
                 for (int i = tid; i < cd.tile_count; i += NT)
-                    comp_add(acc, chain_parts[static_cast<int64_t>(i) * kPart + q]);
+                    comp_add(acc[q], chain_parts[static_cast<int64_t>(i) * kPart + q]);
                 if (tid == 0 && cd.edge_tile >= 0)
-                    comp_add(acc, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + q]);
-                const Comp r = wave_comp_sum(acc);
-                if (lane == 0) part[0][q] = r;
+                    comp_add(acc[q], A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + q]);
+            }
+            wave_comp_sum_n(acc);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) part[0][q] = acc[q];
             }
         }
     } else {
@@ -993,10 +1020,10 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
 #pragma unroll
             for (int q = 0; q < NQ; ++q) comp_add(acc[q], pp[q]);
         }
+        wave_comp_sum_n(acc);
+        if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const Comp r = wave_comp_sum(acc[q]);
-            if (lane == 0) part[wv][q] = r;
+            for (int q = 0; q < NQ; ++q) part[wv][q] = acc[q];
         }
     }
     if constexpr (NT == kWave)
@@ -1011,12 +1038,89 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         for (int w = 1; w < NW; ++w) r = comp_merge(r, part[w][q]);
         tot[q] = r.s + r.c;
     }
-    const double* ce = A.chain_edge + static_cast<int64_t>(c) * kEdge;
-    const double edge[kEdge] = {ce[0], ce[1], ce[2], ce[3]};
-    const double shift_in = A.shift ? A.shift[c] : 0.0;
-    const Decision d = finalize_decide(A, c, cd.T, tot, edge, shift_in, draws);
-    if (d.accepted) A.state_sel[c] ^= 1;
-    if (A.shift) A.shift[c] = d.shift;
+    finalize_commit(A, c, cd.T, tot, draws);
+}
+
+// The split finalize of chains of many tiles: block (s, c) adds slice s
+// (kSliceTiles tiles) of chain c's partials, read coalesced -- thread t holds
+// quantity t % 16 of tiles t / 16 + 16 j -- and stores the slice's compensated
+// sums; the last block of the chain to finish (a per-chain arrival count)
+// merges the slices in order, adds the edge tile, draws the chain's random
+// numbers and runs finalize_commit.  One block per slice spreads the reads of
+// a long chain's partials over many compute units.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
+    static_assert(NT == 256 && kSliceTiles * kPart % NT == 0, "slice layout");
+    constexpr int kLoads = kSliceTiles * kPart / NT;
+    __shared__ Comp part[NT / kWave][kNQ];
+    __shared__ ThetaDraws draws;
+    __shared__ int last;
+    const int c = blockIdx.y;
+    const int sl = blockIdx.x;
+    const ChainDesc cd = A.chains[c];
+    const int n_sl = (cd.tile_count + kSliceTiles - 1) / kSliceTiles;
+    if (sl >= n_sl) return;  // uniform over the block
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int q = tid & (kPart - 1);
+    const int t_lo = sl * kSliceTiles;
+    const int n_here = min(kSliceTiles, cd.tile_count - t_lo);
+    const double* base = A.partials + static_cast<int64_t>(cd.tile_begin + t_lo) * kPart;
+    Comp acc[2] = {Comp{0.0, 0.0}, Comp{0.0, 0.0}};
+    {
+        double v[kLoads];
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) {
+            const int tile = tid / kPart + (NT / kPart) * j;
+            v[j] = (q < kNQ && tile < n_here) ? base[tid + NT * j] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kLoads; ++j) comp_add(acc[j & 1], v[j]);
+    }
+    Comp r = comp_merge(acc[0], acc[1]);
+    // lanes l, l ^ 16, l ^ 32, l ^ 48 of a wavefront hold the same quantity
+#pragma unroll
+    for (int off = kWave / 2; off >= kPart; off >>= 1) {
+        Comp o;
+        o.s = __shfl_xor(r.s, off, kWave);
+        o.c = __shfl_xor(r.c, off, kWave);
+        r = (tid & off) == 0 ? comp_merge(r, o) : comp_merge(o, r);
+    }
+    if (lane < kNQ) part[wv][lane] = r;
+    __syncthreads();
+    double* mine = A.slices + (static_cast<int64_t>(c) + cd.tile_begin / kSliceTiles + sl) * (2 * kNQ);
+    if (tid < kNQ) {
+        Comp m = part[0][tid];
+#pragma unroll
+        for (int w = 1; w < NT / kWave; ++w) m = comp_merge(m, part[w][tid]);
+        mine[2 * tid] = m.s;
+        mine[2 * tid + 1] = m.c;
+    }
+    // publish the slice, then count it; the block that counts the last slice
+    // continues with the whole chain
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(&A.arrive[c], 1u) == static_cast<uint32_t>(n_sl - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (tid == 0) A.arrive[c] = 0u;  // for the next launch
+    const double* first = A.slices + (static_cast<int64_t>(c) + cd.tile_begin / kSliceTiles) * (2 * kNQ);
+    if (tid < kNQ) {
+        Comp m{first[2 * tid], first[2 * tid + 1]};
+        for (int s = 1; s < n_sl; ++s)
+            m = comp_merge(m, Comp{first[s * 2 * kNQ + 2 * tid], first[s * 2 * kNQ + 2 * tid + 1]});
+        if (cd.edge_tile >= 0) comp_add(m, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + tid]);
+        part[0][tid] = m;
+    }
+    finalize_draws(A, c, cd.T, tid, NT, draws);
+    __syncthreads();
+    if (tid != 0) return;
+    double tot[kNQ];
+#pragma unroll
+    for (int k = 0; k < kNQ; ++k) tot[k] = part[0][k].s + part[0][k].c;
+    finalize_commit(A, c, cd.T, tot, draws);
 }
 
 template <int NT>

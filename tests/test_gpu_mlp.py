@@ -137,3 +137,15 @@ def test_training_on_gpu_reduces_loss():
     tg = torch.as_tensor(target.astype(np.float32), device="cuda")
     hist = net.fit(xg, tg, epochs=8, batch=2048, lr=3e-3)
     assert hist[-1] < 0.1 * hist[0], hist
+
+
+def test_clip_passes_non_finite_outputs():
+    """With the clip on, a finite output is clipped to [-5, 5] and a non-finite
+    one (here every output, from a NaN output bias) is passed on unchanged,
+    so that the identity fallback sees it; the oracle does the same."""
+    p = M.init_params(1)
+    p["b3"][:] = np.nan
+    Xb, xg = _inputs(100, 3)
+    net = mass.MassNet(M.flatten(p), np.zeros(27), np.ones(27))
+    assert np.all(np.isnan(net.forward(xg, clip=True).cpu().numpy()))
+    assert np.all(np.isnan(M.log_mass(p, Xb)))

@@ -197,3 +197,16 @@ def test_gradient_fp64_matches_torch_autograd():
     for k in ref:
         np.testing.assert_allclose(g[k], ref[k], rtol=1e-10, atol=1e-13, err_msg=k)
     assert M.loss(p, X, y, bf16=False) == pytest.approx(loss.item(), rel=1e-13)
+
+
+def test_log_mass_clips_finite_outputs_only():
+    """The oracle's log mass: finite outputs clipped to [-5, 5], non-finite
+    ones passed on (the sampler's identity fallback handles them)."""
+    p = M.init_params(4)
+    X = np.zeros((50, 32))
+    X[:, :27] = np.random.default_rng(2).standard_normal((50, 27))
+    p["b3"][:] = 40.0
+    assert np.all(M.log_mass(p, X, bf16=False) == 5.0)
+    p["b3"][:] = np.inf
+    out = M.log_mass(p, X, bf16=False)
+    assert np.all(np.isinf(out))
