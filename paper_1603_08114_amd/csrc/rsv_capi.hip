@@ -460,6 +460,7 @@ TrajArgs<R> traj_args(rsv_ctx* c, uint64_t sweep, const double* p0) {
     a.shift = level_moves(c) ? c->shift : nullptr;
     a.acc_sum = nullptr;
     a.acc_sq = nullptr;
+    a.h_prev_out = nullptr;
     a.terms = c->pb.terms;
     a.integrator = (c->pb.flags & RSV_FLAG_OMELYAN)       ? kIntOmelyan
                    : (c->pb.flags & RSV_FLAG_FOREST_RUTH) ? kIntForestRuth
@@ -485,10 +486,11 @@ rsv_status nonfinite_reported(rsv_ctx* c) {
 
 template <typename R>
 rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, float* acc_sum,
-                           float* acc_sq) {
+                           float* acc_sq, void* h_prev_out) {
     TrajArgs<R> a = traj_args<R>(c, sweep, p0);
     a.acc_sum = acc_sum;
     a.acc_sq = acc_sq;
+    a.h_prev_out = static_cast<R*>(h_prev_out);
     const bool mass = c->log_mass != nullptr;
     const bool timed = c->ev_used < c->ev_start.size();
     if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
@@ -531,13 +533,17 @@ FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do
 
 // acc_sum / acc_sq (or nullptr): accumulators that receive the state this
 // trajectory starts from, i.e. the result of the previous sweep.
+// h_prev_out (or nullptr): receives the state this trajectory starts from
+// (the previous sweep's trace row); h_trace (or nullptr): receives the state
+// after this sweep, by a separate gather.
 rsv_status run_trajectory(rsv_ctx* c, uint64_t sweep, const double* p0, const double* log_u,
                           double* delta_h, int32_t* accepted, int do_theta, rsv_theta* theta_trace,
                           void* h_trace, double* stats_out, float* acc_sum = nullptr,
-                          float* acc_sq = nullptr) {
+                          float* acc_sq = nullptr, void* h_prev_out = nullptr) {
     const rsv_status st =
-        c->pb.precision == RSV_F64 ? launch_traj_all<double>(c, sweep, p0, acc_sum, acc_sq)
-                                   : launch_traj_all<float>(c, sweep, p0, acc_sum, acc_sq);
+        c->pb.precision == RSV_F64
+            ? launch_traj_all<double>(c, sweep, p0, acc_sum, acc_sq, h_prev_out)
+            : launch_traj_all<float>(c, sweep, p0, acc_sum, acc_sq, h_prev_out);
     if (st != RSV_OK) return st;
     FinalizeArgs f = finalize_args(c, sweep, 1, do_theta);
     f.log_u = log_u;
@@ -837,14 +843,18 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
         double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
         int32_t* ac = (trace && trace->accepted) ? trace->accepted + ofs : nullptr;
         rsv_theta* tt = (trace && trace->theta) ? trace->theta + ofs : nullptr;
-        void* ht = (trace && trace->h)
-                       ? static_cast<char*>(trace->h) + static_cast<size_t>(i) * c->n_state * elem
-                       : nullptr;
+        auto h_row = [&](int32_t r) -> void* {
+            return static_cast<char*>(trace->h) + static_cast<size_t>(r) * c->n_state * elem;
+        };
+        const bool rec_h = trace && trace->h;
         // the trajectory of sweep i accumulates the state after sweep i - 1
+        // and writes it to that sweep's trace row; the last row is gathered
         const bool add = acc && i > 0;
         st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
-                            update_theta ? 1 : 0, tt, ht, nullptr, add ? acc_sum_f : nullptr,
-                            add ? acc_sq_f : nullptr);
+                            update_theta ? 1 : 0, tt,
+                            rec_h && i == n_sweeps - 1 ? h_row(i) : nullptr, nullptr,
+                            add ? acc_sum_f : nullptr, add ? acc_sq_f : nullptr,
+                            rec_h && i > 0 ? h_row(i - 1) : nullptr);
         if (st != RSV_OK) return st;
         if (add && (i - 1) % bl == bl - 1) RSV_HIP(flush(i - 1));
     }

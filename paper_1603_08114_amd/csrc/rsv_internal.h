@@ -76,6 +76,8 @@ struct TrajArgs {
                                 // state (value = stored + shift), or nullptr
     float* acc_sum;             // per state entry: add the state the trajectory
     float* acc_sq;              // starts from, and its square (or nullptr)
+    R* h_prev_out;              // per state entry: the state the trajectory starts
+                                // from (the previous sweep's trace row), or nullptr
     int32_t terms;
     int32_t integrator;         // kIntLeapfrog, kIntOmelyan or kIntForestRuth
     uint32_t* counters;         // kCntNonfiniteState is set on a non-finite state

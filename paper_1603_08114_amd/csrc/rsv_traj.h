@@ -243,7 +243,8 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     // batch-means accumulators of the starting state (the previous sweep's
     // result) on the exact sites: the read-modify-writes overlap with the
     // momentum draw instead of costing a separate pass over the state
-    if (A.acc_sum || A.acc_sq) {
+    // (and the trace row of the previous sweep, the same values)
+    if (A.acc_sum || A.acc_sq || A.h_prev_out) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const int t = t0 + j;
@@ -252,6 +253,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
                 const int64_t i = cd.h_off + t;
                 if (A.acc_sum) A.acc_sum[i] += v;
                 if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, A.acc_sq[i]);
+                if (A.h_prev_out) A.h_prev_out[i] = h[j];
             }
         }
     }
