@@ -234,7 +234,7 @@ hipError_t launch_finalize(hipStream_t st, const FinalizeArgs& a, int32_t max_ti
     // chains of at most 128 tiles: one wavefront each; longer chains: the
     // split finalize, one block per slice of kSliceTiles tiles
     if (max_tiles_per_chain <= 128 || !a.slices) {
-        hipLaunchKernelGGL(k_finalize<64>, dim3(a.n_chains), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_finalize, dim3(a.n_chains), dim3(2 * kWave), 0, st, a);
     } else {
         const int n_sl = (max_tiles_per_chain + kSliceTiles - 1) / kSliceTiles;
         hipLaunchKernelGGL(k_finalize_split<256>, dim3(n_sl, a.n_chains), dim3(256), 0, st, a);

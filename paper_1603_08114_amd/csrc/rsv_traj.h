@@ -926,10 +926,13 @@ __device__ __forceinline__ void finalize_commit(const FinalizeArgs& A, const int
 
 // Everything the finalize does for chain c, by NT threads (tid = 0..NT-1;
 // NT = 64: one wavefront, which may be one of several in its block) with
-// shared scratch passed in; returns in every thread.
-template <int NT>
+// shared scratch passed in; returns in every thread.  With OWN_DRAWS false
+// (NT = 64) another wavefront of the block fills `draws` meanwhile, and the
+// wavefront meets it at a block barrier before the decision.
+template <int NT, bool OWN_DRAWS = true>
 __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[NT / kWave][kNQ],
                                ThetaDraws& draws, const int tid) {
+    static_assert(OWN_DRAWS || NT == kWave, "split draws: one reducing wavefront");
     constexpr int NW = NT / kWave;
     constexpr int NQ = kNQ;
     const int lane = tid & (kWave - 1);
@@ -953,7 +956,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
                 v[q] = has ? pt[q] : 0.0;
                 ve[q] = has_edge ? pe[q] : 0.0;
             }
-            finalize_draws(A, c, cd.T, tid, NT, draws);
+            if constexpr (OWN_DRAWS) finalize_draws(A, c, cd.T, tid, NT, draws);
             Comp acc[NQ];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -974,7 +977,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
                 for (int q = 0; q < NQ; ++q) part[0][q] = acc[q];
             }
         } else {
-            finalize_draws(A, c, cd.T, tid, NT, draws);
+            if constexpr (OWN_DRAWS) finalize_draws(A, c, cd.T, tid, NT, draws);
             Comp acc[NQ];
             for (int q = 0; q < NQ; ++q) {
                 acc[q] = Comp{0.0, 0.0};
@@ -990,7 +993,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
             }
         }
     } else {
-        finalize_draws(A, c, cd.T, tid, NT, draws);
+        if constexpr (OWN_DRAWS) finalize_draws(A, c, cd.T, tid, NT, draws);
         Comp acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = Comp{0.0, 0.0};
@@ -1028,7 +1031,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
             for (int q = 0; q < NQ; ++q) part[wv][q] = acc[q];
         }
     }
-    if constexpr (NT == kWave)
+    if constexpr (NT == kWave && OWN_DRAWS)
         wave_sync();
     else
         __syncthreads();
@@ -1125,11 +1128,19 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     finalize_commit(A, c, cd.T, tot, draws);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_finalize(FinalizeArgs A) {
-    __shared__ Comp part[NT / kWave][kNQ];
+// One chain per block of two wavefronts: the first loads and adds the tile
+// partials while the second evaluates the chain's random numbers (the two
+// are independent), then the first wavefront's lane 0 decides.
+__global__ __launch_bounds__(2 * kWave) void k_finalize(FinalizeArgs A) {
+    __shared__ Comp part[1][kNQ];
     __shared__ ThetaDraws draws;
-    finalize_chain<NT>(A, blockIdx.x, part, draws, threadIdx.x);
+    const int c = blockIdx.x;
+    if (threadIdx.x >= kWave) {
+        finalize_draws(A, c, A.chains[c].T, threadIdx.x - kWave, kWave, draws);
+        __syncthreads();  // meets the first wavefront's barrier before the decision
+        return;
+    }
+    finalize_chain<kWave, false>(A, c, part, draws, threadIdx.x);
 }
 
 }  // namespace
