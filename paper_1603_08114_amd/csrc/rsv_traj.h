@@ -1050,8 +1050,9 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
 // (kSliceTiles tiles) of chain c's partials, read coalesced -- thread t holds
 // quantity t % 16 of tiles t / 16 + 16 j -- and stores the slice's compensated
 // sums; the last block of the chain to finish (a per-chain arrival count)
-// merges the slices in order, adds the edge tile, draws the chain's random
-// numbers and runs finalize_commit.  One block per slice spreads the reads of
+// merges the slices in order and adds the edge tile (first wavefront) while
+// its other wavefronts draw the chain's random numbers, then runs
+// finalize_commit.  One block per slice spreads the reads of
 // a long chain's partials over many compute units.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
@@ -1119,7 +1120,8 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
         if (cd.edge_tile >= 0) comp_add(m, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + tid]);
         part[0][tid] = m;
     }
-    finalize_draws(A, c, cd.T, tid, NT, draws);
+    // the random numbers by the other wavefronts, while the first merges
+    if (tid >= kWave) finalize_draws(A, c, cd.T, tid - kWave, NT - kWave, draws);
     __syncthreads();
     if (tid != 0) return;
     double tot[kNQ];
