@@ -170,6 +170,21 @@ __device__ inline void wave_comp_sum_n(Comp (&v)[N], int top = kWave / 2) {
     }
 }
 
+// wave_sum of N quantities at once: the butterflies interleave, each
+// quantity's additions are those of wave_sum.
+template <int N>
+__device__ inline void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const bool low = (threadIdx.x & off) == 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const double o = __shfl_xor(v[q], off, kWave);
+            v[q] = low ? (v[q] + o) : (o + v[q]);
+        }
+    }
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {

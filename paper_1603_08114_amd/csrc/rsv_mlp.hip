@@ -25,7 +25,8 @@ constexpr int kParams = RSV_MLP_PARAMS;
 constexpr int oW1 = 0, oB1 = kInPad * kHid, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid,
               oW3 = oB2 + kHid, oB3 = oW3 + kHid;
 static_assert(oB3 + 1 == kParams, "parameter layout");
-constexpr int kRows = 64;            // rows per block
+constexpr int kRows = 64;            // rows per block (per chunk, for inference)
+constexpr int64_t kForwardBlocks = 1024;  // inference grid: 4 blocks per compute unit
 constexpr int kPartial = kParams + 1;  // gradient + loss per block
 constexpr int kWindow = 5;
 constexpr double kY2Floor = 1e-8;
@@ -41,10 +42,29 @@ __device__ inline uint16_t to_bf16(float f) {  // round to nearest, ties to even
 }
 __device__ inline float from_bf16(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
 
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf in FP32 without branches: Hastings' rational approximation
+// (Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.26),
+// erf(z) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) e^{-z^2},
+// t = 1 / (1 + p z) for z >= 0, odd in z; absolute error <= 1.5e-7, far
+// below the bfloat16 rounding the activations receive.  A library erff
+// branches on the argument's range, and the lanes of a wavefront take every
+// branch.
+__device__ inline float erf_fast(float x) {
+    const float z = __builtin_fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, z, 1.0f));
+    float q = 1.061405429f;
+    q = __builtin_fmaf(q, t, -1.453152027f);
+    q = __builtin_fmaf(q, t, 1.421413741f);
+    q = __builtin_fmaf(q, t, -0.284496736f);
+    q = __builtin_fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);
+    const float r = __builtin_fmaf(-q * t, e, 1.0f);
+    return __builtin_copysignf(r, x);
+}
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erf_fast(x * 0.70710678118654752f)); }
 __device__ inline float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-           x * expf(-0.5f * x * x) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_fast(x * 0.70710678118654752f)) +
+           x * __builtin_amdgcn_exp2f(-0.5f * x * x * 1.4426950408889634f) * 0.39894228040143268f;
 }
 
 __device__ inline bf16x8 load8(const uint16_t* p) {  // 16-byte aligned
@@ -101,77 +121,88 @@ __global__ __launch_bounds__(256) void k_mlp(int64_t n, const uint16_t* __restri
     load_weights(W, P, TRAIN);
     __syncthreads();
 
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows + wv * 16;
     auto src_row = [&](int64_t i) -> int64_t { return rows ? static_cast<int64_t>(rows[i]) : i; };
-
-    // ---- layer 1: [16 x 32] x [32 x 64] ----
-    bf16x8 a1;
-    {
-        const int64_t ri = row0 + r;
-        if (ri < n) {
-            a1 = load8(X + src_row(ri) * kInPad + 8 * q);
-        } else {
-            const uint4 z = {0u, 0u, 0u, 0u};
-            a1 = __builtin_bit_cast(bf16x8, z);
-        }
-    }
     float pre1[4][4], pre2[4][4];
     uint16_t h1b[4][4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, load8(&W.w1t[16 * nt + r][8 * q]),
-                                                                zero, 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            pre1[nt][j] = d[j] + W.b1[16 * nt + r];
-            h1b[nt][j] = to_bf16(gelu(pre1[nt][j]));
-            W.tb[wv][4 * q + j][16 * nt + r] = h1b[nt][j];
-        }
-    }
-    __syncthreads();
-
-    // ---- layer 2: [16 x 64] x [64 x 64] ----
-    const bf16x8 a2_0 = load8(&W.tb[wv][r][8 * q]);
-    const bf16x8 a2_1 = load8(&W.tb[wv][r][32 + 8 * q]);
     float h2f[4][4];
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-        f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2_0, load8(&W.w2t[16 * nt + r][8 * q]),
-                                                          zero, 0, 0, 0);
-        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2_1, load8(&W.w2t[16 * nt + r][32 + 8 * q]),
-                                                    d, 0, 0, 0);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            pre2[nt][j] = d[j] + W.b2[16 * nt + r];
-            h2f[nt][j] = from_bf16(to_bf16(gelu(pre2[nt][j])));
-        }
-    }
-
-    // ---- layer 3: dot with w3 over the 64 columns (16 lanes x 4 tiles) ----
     float o[4];
+    // the forward pass of the 16 rows from row0 of this wavefront (the block's
+    // 64 rows from the chunk's first row)
+    auto forward = [&](const int64_t row0) {
+        // ---- layer 1: [16 x 32] x [32 x 64] ----
+        bf16x8 a1;
+        {
+            const int64_t ri = row0 + r;
+            if (ri < n) {
+                a1 = load8(X + src_row(ri) * kInPad + 8 * q);
+            } else {
+                const uint4 z = {0u, 0u, 0u, 0u};
+                a1 = __builtin_bit_cast(bf16x8, z);
+            }
+        }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) s += h2f[nt][j] * W.w3[16 * nt + r];
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
-        o[j] = s + W.b3;
-    }
-
-    if constexpr (!TRAIN) {
-        if (r == 0) {
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a1, load8(&W.w1t[16 * nt + r][8 * q]), zero, 0, 0, 0);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t ri = row0 + 4 * q + j;
-                // a non-finite output is passed on as it is, for the caller's fallback
-                if (ri < n) out[ri] = clip && isfinite(o[j]) ? fminf(fmaxf(o[j], -5.0f), 5.0f) : o[j];
+                pre1[nt][j] = d[j] + W.b1[16 * nt + r];
+                h1b[nt][j] = to_bf16(gelu(pre1[nt][j]));
+                W.tb[wv][4 * q + j][16 * nt + r] = h1b[nt][j];
+            }
+        }
+        __syncthreads();
+
+        // ---- layer 2: [16 x 64] x [64 x 64] ----
+        const bf16x8 a2_0 = load8(&W.tb[wv][r][8 * q]);
+        const bf16x8 a2_1 = load8(&W.tb[wv][r][32 + 8 * q]);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a2_0, load8(&W.w2t[16 * nt + r][8 * q]), zero, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a2_1, load8(&W.w2t[16 * nt + r][32 + 8 * q]), d, 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                pre2[nt][j] = d[j] + W.b2[16 * nt + r];
+                h2f[nt][j] = from_bf16(to_bf16(gelu(pre2[nt][j])));
+            }
+        }
+
+        // ---- layer 3: dot with w3 over the 64 columns (16 lanes x 4 tiles) ----
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float s = 0.f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) s += h2f[nt][j] * W.w3[16 * nt + r];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
+            o[j] = s + W.b3;
+        }
+    };
+    if constexpr (!TRAIN) {
+        // inference: each block stages the weights once and takes chunks of
+        // kRows rows with a stride of the grid
+        const int64_t n_chunks = (n + kRows - 1) / kRows;
+        for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+            const int64_t row0 = chunk * kRows + wv * 16;
+            forward(row0);
+            if (r == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t ri = row0 + 4 * q + j;
+                    // a non-finite output is passed on as it is, for the caller's fallback
+                    if (ri < n)
+                        out[ri] = clip && isfinite(o[j]) ? fminf(fmaxf(o[j], -5.0f), 5.0f) : o[j];
+                }
             }
         }
         return;
     } else {
+        const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kRows + wv * 16;
+        forward(row0);
         // ---- d loss / d out for the four rows this lane's group holds ----
         const float inv_n = 1.0f / static_cast<float>(n);
         float dout[4], sq = 0.f;
@@ -409,7 +440,9 @@ rsv_status rsv_mlp_forward(int64_t n, const uint16_t* x, const float* params, fl
         return set_error(RSV_EINVAL, "rsv_mlp_forward", "need n >= 1 and non-NULL pointers");
     if (reinterpret_cast<uintptr_t>(x) % 16)
         return set_error(RSV_EINVAL, "rsv_mlp_forward", "x must be 16-byte aligned");
-    hipLaunchKernelGGL(k_mlp<false>, dim3(static_cast<unsigned>(n_blocks(n))), dim3(256), 0,
+    // a few blocks per compute unit, each looping over its chunks of rows
+    const int64_t grid = n_blocks(n) < kForwardBlocks ? n_blocks(n) : kForwardBlocks;
+    hipLaunchKernelGGL(k_mlp<false>, dim3(static_cast<unsigned>(grid)), dim3(256), 0,
                        static_cast<hipStream_t>(hip_stream), n, x, nullptr, nullptr, params, out,
                        clip, nullptr);
     MLP_HIP(hipGetLastError());

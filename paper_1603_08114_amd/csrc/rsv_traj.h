@@ -499,14 +499,15 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     }
 
     double red[kNQ];
-    red[kPartDH] = wave_sum(D.dH);
-    red[kPartSyProp] = wave_sum(D.sy1);
-    red[kPartSyCur] = wave_sum(D.sy0);
+    red[kPartDH] = D.dH;
+    red[kPartSyProp] = D.sy1;
+    red[kPartSyCur] = D.sy0;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        red[kPartProp + q] = wave_sum(D.s1[q]);
-        red[kPartCur + q] = wave_sum(D.s0[q]);
+        red[kPartProp + q] = D.s1[q];
+        red[kPartCur + q] = D.s0[q];
     }
+    wave_sum_n(red);
     if constexpr (NW > 1) {
         if (lane == 0) {
 #pragma unroll
