@@ -247,8 +247,14 @@ def small_chain(jit, level, with_oracle, integrator="leapfrog"):
     theta = dict(synth.THETA_STAR)
     y, lr, h_true = synth.simulate_rsv(T, theta, 1)
     flags = (RSV_FLAG_LEVEL_MOVE if level else 0) | iflag
+    # the tile shape by timing sweeps of every compiled shape (one T = 1000
+    # chain is latency-bound: four single-wavefront tiles without barriers
+    # beat one four-wavefront tile)
+    from paper_1603_08114_amd import autotune
+    S_t, NW_t, _ = autotune.best_shape([0, T], y, lr, h_true, theta, (k, dtau), n_sweeps=50,
+                                       seed=1, dtau_jitter=jit, flags=flags)
     smp = api.RSVSampler([0, T], y, lr, h_true, theta, max_steps=k, seed=1, dtau_jitter=jit,
-                         flags=flags)
+                         flags=flags, sites_per_lane=S_t, waves_per_tile=NW_t)
     smp.sweep(0, burn, (k, dtau), update_theta=True, record=())
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -267,7 +273,7 @@ def small_chain(jit, level, with_oracle, integrator="leapfrog"):
                                      map(float, ess_th))),
            "acceptance": float(out["accepted"].float().mean().item()),
            "site_updates_per_s": T * k * n / elapsed, "k": k, "dtau": dtau,
-           "integrator": integrator}
+           "integrator": integrator, "sites_per_lane": S_t, "waves_per_tile": NW_t}
     smp.close()
     ref = None
     if with_oracle:
