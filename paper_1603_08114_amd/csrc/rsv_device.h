@@ -22,6 +22,20 @@ enum : uint64_t { kTagMomentum = 0, kTagAccept = 1, kTagTheta = 2, kTagStep = 3,
 // round multipliers (full 128-bit products), swaps and xors with the key;
 // the key advances by the two Weyl constants after every round.
 // ---------------------------------------------------------------------------
+// Full 128-bit product m * x as (hi, lo) from four 32 x 32 -> 64 products,
+// each with a 32-bit addend that cannot overflow it (one v_mad_u64_u32
+// apiece): m x = xh mh 2^64 + (xh ml + xl mh) 2^32 + xl ml.
+__device__ __forceinline__ void mulhilo64(uint64_t m, uint64_t x, uint64_t& hi, uint64_t& lo) {
+    const uint32_t ml = static_cast<uint32_t>(m), mh = static_cast<uint32_t>(m >> 32);
+    const uint32_t xl = static_cast<uint32_t>(x), xh = static_cast<uint32_t>(x >> 32);
+    const uint64_t t = static_cast<uint64_t>(xl) * ml;
+    const uint64_t u = static_cast<uint64_t>(xl) * mh + (t >> 32);
+    const uint64_t v = static_cast<uint64_t>(xh) * ml + static_cast<uint32_t>(u);
+    const uint64_t w = static_cast<uint64_t>(xh) * mh + (u >> 32);
+    hi = w + (v >> 32);
+    lo = (v << 32) | static_cast<uint32_t>(t);
+}
+
 struct Philox4x64 {
     uint64_t w[4];
 
@@ -33,8 +47,9 @@ struct Philox4x64 {
         const uint64_t weyl_b = 0xBB67AE8584CAA73Bull;
 #pragma unroll
         for (int round = 0; round < 10; ++round) {
-            const uint64_t hi_a = __umul64hi(mul_a, c0), lo_a = mul_a * c0;
-            const uint64_t hi_b = __umul64hi(mul_b, c2), lo_b = mul_b * c2;
+            uint64_t hi_a, lo_a, hi_b, lo_b;
+            mulhilo64(mul_a, c0, hi_a, lo_a);
+            mulhilo64(mul_b, c2, hi_b, lo_b);
             const uint64_t n0 = hi_b ^ c1 ^ k0;
             const uint64_t n2 = hi_a ^ c3 ^ k1;
             c0 = n0;
@@ -70,6 +85,37 @@ __device__ inline void gauss_pair(double u0, double u1, double& z0, double& z1) 
     sincos_2pi(u1, s, c);
     z0 = radius * c;
     z1 = radius * s;
+}
+
+// Box-Muller in FP32, for momenta of the FP32-mixed path: the same uniforms
+// as gauss_pair, rounded to FP32 (u0 keeps its full range, so the tail of
+// the radius does too), the radius from the hardware base-2 logarithm and
+// square root (sqrt(-2 ln2 log2 u0)), the angle by sincos_2pi_f32.  The
+// normals agree with gauss_pair's to a few FP32 ulps.
+__device__ inline void gauss_pair_f32(double u0, double u1, float& z0, float& z1) {
+    const float l2 = __builtin_amdgcn_logf(static_cast<float>(u0));
+    const float radius = __builtin_amdgcn_sqrtf(-1.38629436112f * l2);
+    float s, c;
+    sincos_2pi_f32(static_cast<float>(u1), s, c);
+    z0 = radius * c;
+    z1 = radius * s;
+}
+
+// Momentum normals of block idx (sites 4 idx .. 4 idx + 3) of a chain's
+// stream, in the path's precision: FP64 by gauss_pair, FP32 by
+// gauss_pair_f32.  The trajectory kernel and rsv_hmc_momenta both draw here.
+template <typename R>
+__device__ inline void momentum_normals(uint64_t seed, uint64_t idx, uint64_t sweep,
+                                        uint64_t chain, R z[4]) {
+    double u[4];
+    uniforms4(seed, idx, sweep, chain, kTagMomentum, u);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        gauss_pair(u[0], u[1], z[0], z[1]);
+        gauss_pair(u[2], u[3], z[2], z[3]);
+    } else {
+        gauss_pair_f32(u[0], u[1], z[0], z[1]);
+        gauss_pair_f32(u[2], u[3], z[2], z[3]);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -28,7 +28,10 @@ namespace rsv {
 // diverged trajectory produces -- would add a meaningless n to the exponent
 // of an infinite polynomial value and return an arbitrary finite number,
 // and dH must be +inf or NaN there so that the proposal is rejected.)
-// Worst relative error on |x| <= 700: 4.7e-16 (4 ulp).
+// Worst relative error on |x| <= 700: 4.7e-16 (4 ulp).  exp_fast<false>
+// leaves out the clamp and the saturation, which change nothing for
+// |x| <= 708: for callers that have checked the range of their arguments.
+template <bool SATURATE = true>
 __device__ __forceinline__ double exp_fast(double x) {
     const double log2e = 0x1.71547652b82fep+0;
     const double ln2_hi = 0x1.62e42fefa39efp-1;
@@ -50,6 +53,8 @@ __device__ __forceinline__ double exp_fast(double x) {
     p = __builtin_fma(p, r, 1.0000000000000067);
     p = __builtin_fma(p, r, 1.0);
     int ni = __double2loint(t);
+    if constexpr (!SATURATE)
+        return __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
     ni = ni < -1022 ? -1022 : (ni > 1023 ? 1023 : ni);
     const double e = __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
     // x * inf is +inf for x > 0 and NaN for a NaN x
@@ -57,14 +62,16 @@ __device__ __forceinline__ double exp_fast(double x) {
     return x < -745.1332191019412 ? 0.0 : hi;
 }
 
-// e^x in FP64 for the leapfrog force only, one instruction shorter than
-// exp_fast: ln2 is taken as its FP64 value alone (n ln2 then carries
-// |n| * 2.3e-17 of error) and P is the degree-9 minimax polynomial (relative
-// error 1.4e-14); n is clamped and 2^n applied as in exp_fast.  The force may
-// be any function of position without affecting the exactness of the chain
-// (dH is formed with exp_fast); at |x| <= 30 the relative error stays below
-// 1.5e-14, which moves h after a trajectory by orders of magnitude less than
-// 1e-12 of its scale.
+// e^x in FP64 for the leapfrog force only, shorter than exp_fast: ln2 is
+// taken as its FP64 value alone (n ln2 then carries |n| * 2.3e-17 of error),
+// P is the degree-9 minimax polynomial (relative error 1.4e-14), and n is
+// not clamped, so the value is e^x only for |x| <= 708; beyond that (a
+// trajectory that has already diverged) it is some other number, still a
+// function of x alone.  The force may be any function of position without
+// affecting the exactness of the chain (the leapfrog stays reversible and
+// volume preserving, and dH is formed with the saturating exp_fast); at
+// |x| <= 30 the relative error stays below 1.5e-14, which moves h after a
+// trajectory by orders of magnitude less than 1e-12 of its scale.
 __device__ __forceinline__ double exp_force(double x) {
     const double log2e = 0x1.71547652b82fep+0;
     const double ln2 = 0x1.62e42fefa39efp-1;
@@ -82,8 +89,7 @@ __device__ __forceinline__ double exp_force(double x) {
     p = __builtin_fma(p, r, 0.4999999999944855);
     p = __builtin_fma(p, r, 0.999999999999893);
     p = __builtin_fma(p, r, 1.000000000000013);
-    int ni = __double2loint(t);
-    ni = ni < -1022 ? -1022 : (ni > 1023 ? 1023 : ni);
+    const int ni = __double2loint(t);
     return __hiloint2double(__double2hiint(p) + (ni << 20), __double2loint(p));
 }
 
@@ -148,6 +154,32 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
     const int q = static_cast<int>(k) & 3;
     const double s_sel = (q & 1) ? c : s;
     const double c_sel = (q & 1) ? s : c;
+    sn = (q & 2) ? -s_sel : s_sel;
+    cs = ((q + 1) & 2) ? -c_sel : c_sel;
+}
+
+// sin and cos of 2 pi u in FP32 for u in [0, 1]: 4u = k + r exactly, angle
+// th = r pi/2 in [-pi/4, pi/4], Taylor series through th^9 (sin) and th^10
+// (cos) (truncation below 2e-9), then the quadrant k.
+__device__ __forceinline__ void sincos_2pi_f32(float u, float& sn, float& cs) {
+    const float x4 = 4.0f * u;
+    const float k = __builtin_rintf(x4);
+    const float th = (x4 - k) * 1.57079632679489662f;
+    const float t2 = th * th;
+    float ps = 1.0f / 362880.0f;
+    ps = __builtin_fmaf(ps, t2, -1.0f / 5040.0f);
+    ps = __builtin_fmaf(ps, t2, 1.0f / 120.0f);
+    ps = __builtin_fmaf(ps, t2, -1.0f / 6.0f);
+    const float s = __builtin_fmaf(th * t2, ps, th);
+    float pc = -1.0f / 3628800.0f;
+    pc = __builtin_fmaf(pc, t2, 1.0f / 40320.0f);
+    pc = __builtin_fmaf(pc, t2, -1.0f / 720.0f);
+    pc = __builtin_fmaf(pc, t2, 1.0f / 24.0f);
+    pc = __builtin_fmaf(pc, t2, -0.5f);
+    const float c = __builtin_fmaf(t2, pc, 1.0f);
+    const int q = static_cast<int>(k) & 3;
+    const float s_sel = (q & 1) ? c : s;
+    const float c_sel = (q & 1) ? s : c;
     sn = (q & 2) ? -s_sel : s_sel;
     cs = ((q + 1) & 2) ? -c_sel : c_sel;
 }

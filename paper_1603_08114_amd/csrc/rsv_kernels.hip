@@ -118,15 +118,13 @@ __global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const 
     const int n_blocks = (cd.T + 3) / 4;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_blocks;
          g += gridDim.x * blockDim.x) {
-        double u[4], z[4];
-        uniforms4(seed, static_cast<uint64_t>(g), sweep, static_cast<uint64_t>(c), kTagMomentum, u);
-        gauss_pair(u[0], u[1], z[0], z[1]);
-        gauss_pair(u[2], u[3], z[2], z[3]);
+        M z[4];
+        momentum_normals<M>(seed, static_cast<uint64_t>(g), sweep, static_cast<uint64_t>(c), z);
         for (int q = 0; q < 4; ++q) {
             const int t = 4 * g + q;
             if (t >= cd.T) break;
-            const double sm = mass_sqrt ? static_cast<double>(mass_sqrt[cd.d_off + t]) : 1.0;
-            p_out[cd.h_off + t] = z[q] * sm;
+            const M pm = mass_sqrt ? z[q] * mass_sqrt[cd.d_off + t] : z[q];
+            p_out[cd.h_off + t] = static_cast<double>(pm);
         }
     }
 }
