@@ -250,10 +250,23 @@ struct rsv_ctx {
     std::vector<hipEvent_t> ev_start, ev_stop;
     std::vector<int64_t> ev_trajectories;  // trajectories each recorded pair covers
     size_t ev_used = 0;
+    // Sweeps in two chain groups: chains [0, split) on `stream` and
+    // [split, n_chains) on `side`, forked from and joined to `stream` by
+    // events at each rsv_hmc_sweep call, so that one group's finalize (a
+    // short, latency-bound launch) and the tail of its trajectory launch run
+    // beside the other group's trajectory.  The tiles of each group are
+    // contiguous in the tile list (group_tile_first / group_tiles).
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int32_t split = 0;  // == n_chains: one group
+    int32_t group_tile_first[2] = {0, 0}, group_tiles[2] = {0, 0};
 
     ~rsv_ctx() {
         for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
         for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -357,9 +370,9 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
         if (!(lf[s].dtau > 0.0) || !std::isfinite(lf[s].dtau))
             return fail(RSV_EINVAL, "series %d: dtau must be finite and > 0", s);
     }
-    std::vector<TileDesc> body, edges;
     std::vector<ChainDesc> chains(c->n_chains);
-    std::vector<int32_t> edge_of(c->n_chains, -1);
+    std::vector<std::vector<TileDesc>> body_of(c->n_chains), edge_of(c->n_chains);
+    int64_t n_total = 0;
     for (int s = 0; s < c->pb.n_series; ++s) {
         const int32_t T = static_cast<int32_t>(c->offsets[s + 1] - c->offsets[s]);
         for (int j = 0; j < c->C; ++j) {
@@ -369,39 +382,59 @@ rsv_status build_tiles(rsv_ctx* c, const rsv_leapfrog* lf) {
             d.d_off = c->offsets[s];
             d.T = T;
             d.series = s;
-            d.tile_begin = static_cast<int32_t>(body.size());
-            const size_t n_edge_before = edges.size();
-            if (!tile_chain(ch, T, c->S, c->NW, kicks_for(c->pb.flags, lf[s].n_steps), body,
-                            edges))
+            if (!tile_chain(ch, T, c->S, c->NW, kicks_for(c->pb.flags, lf[s].n_steps), body_of[ch],
+                            edge_of[ch]))
                 return fail(RSV_EINVAL, "series %d: n_steps %d too large for a tile", s,
                             lf[s].n_steps);
-            d.tile_count = static_cast<int32_t>(body.size()) - d.tile_begin;
-            if (edges.size() > n_edge_before) edge_of[ch] = static_cast<int32_t>(n_edge_before);
             d.n_steps = lf[s].n_steps;
             d.dtau = lf[s].dtau;
+            n_total += static_cast<int64_t>(body_of[ch].size() + edge_of[ch].size());
         }
     }
-    const int32_t n_total = static_cast<int32_t>(body.size() + edges.size());
     if (n_total > c->lay.max_tiles) return fail(RSV_ENOMEM, "tile count exceeds the workspace");
-    // edge tiles (slower per site) go first so that they start in the first round
-    const int32_t n_edge = static_cast<int32_t>(edges.size());
-    for (int32_t ch = 0; ch < c->n_chains; ++ch) {
-        chains[ch].edge_tile = edge_of[ch];
-        chains[ch].tile_begin += n_edge;
+    // two groups of about half the tiles each when there is a side stream and
+    // more than one chain; otherwise one
+    c->split = c->n_chains;
+    if (c->side && c->n_chains >= 2) {
+        int64_t run = 0;
+        int32_t ch = 0;
+        while (ch < c->n_chains - 1 && 2 * run < n_total) {
+            run += static_cast<int64_t>(body_of[ch].size() + edge_of[ch].size());
+            ++ch;
+        }
+        c->split = std::max<int32_t>(1, ch);
+    }
+    // tile list: per group, its edge tiles (slower per site, so they start
+    // in the first round) and then its body tiles, chain by chain
+    std::vector<TileDesc> tiles;
+    tiles.reserve(static_cast<size_t>(n_total));
+    c->n_body = c->n_edge = 0;
+    for (int g = 0; g < 2; ++g) {
+        const int32_t lo = g == 0 ? 0 : c->split, hi = g == 0 ? c->split : c->n_chains;
+        c->group_tile_first[g] = static_cast<int32_t>(tiles.size());
+        for (int32_t ch = lo; ch < hi; ++ch) {
+            chains[ch].edge_tile = edge_of[ch].empty() ? -1 : static_cast<int32_t>(tiles.size());
+            for (const TileDesc& t : edge_of[ch]) tiles.push_back(t);
+            c->n_edge += static_cast<int32_t>(edge_of[ch].size());
+        }
+        for (int32_t ch = lo; ch < hi; ++ch) {
+            chains[ch].tile_begin = static_cast<int32_t>(tiles.size());
+            chains[ch].tile_count = static_cast<int32_t>(body_of[ch].size());
+            for (const TileDesc& t : body_of[ch]) tiles.push_back(t);
+            c->n_body += static_cast<int32_t>(body_of[ch].size());
+        }
+        c->group_tiles[g] = static_cast<int32_t>(tiles.size()) - c->group_tile_first[g];
     }
     c->max_tiles_per_chain = 0;
     for (const ChainDesc& d : chains)
         c->max_tiles_per_chain = std::max(c->max_tiles_per_chain, d.tile_count + 1);
-    c->n_body = static_cast<int32_t>(body.size());
-    c->n_edge = static_cast<int32_t>(edges.size());
     c->n_bins = 0;
     std::vector<BinDesc> bins;
     std::vector<int32_t> bin_chains, bin_tiles;
     if (c->max_tiles_per_chain - 1 <= kBinMaxChainTiles &&
         bin_shape_available(c->pb.precision, c->S, c->NW))
         pack_bins(chains, c->NW == 1 ? 4 : 1, bins, bin_chains, bin_tiles);
-    c->h_tiles = edges;
-    c->h_tiles.insert(c->h_tiles.end(), body.begin(), body.end());
+    c->h_tiles = std::move(tiles);
     c->h_chains = chains;
     RSV_HIP(hipMemcpyAsync(c->tiles, c->h_tiles.data(), c->h_tiles.size() * sizeof(TileDesc),
                            hipMemcpyHostToDevice, c->stream));
@@ -484,29 +517,39 @@ rsv_status nonfinite_reported(rsv_ctx* c) {
     return RSV_OK;
 }
 
+// Trajectory kernel over tiles [first, first + count) of the list, on `st`.
 template <typename R>
-rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, float* acc_sum,
-                           float* acc_sq, void* h_prev_out) {
+rsv_status launch_traj_tiles(rsv_ctx* c, hipStream_t st, int32_t first, int32_t count,
+                             uint64_t sweep, const double* p0, float* acc_sum, float* acc_sq,
+                             void* h_prev_out) {
     TrajArgs<R> a = traj_args<R>(c, sweep, p0);
     a.acc_sum = acc_sum;
     a.acc_sq = acc_sq;
     a.h_prev_out = static_cast<R*>(h_prev_out);
     const bool mass = c->log_mass != nullptr;
     const bool timed = c->ev_used < c->ev_start.size();
-    if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], c->stream));
-    a.tile_first = 0;
-    a.n_list = c->n_body + c->n_edge;
-    RSV_HIP(launch_traj(c->stream, c->pb.precision, c->S, c->NW, mass, &a));
+    if (timed) RSV_HIP(hipEventRecord(c->ev_start[c->ev_used], st));
+    a.tile_first = first;
+    a.n_list = count;
+    RSV_HIP(launch_traj(st, c->pb.precision, c->S, c->NW, mass, &a));
     if (timed) {
-        RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used], c->stream));
+        RSV_HIP(hipEventRecord(c->ev_stop[c->ev_used], st));
         c->ev_trajectories[c->ev_used++] = 1;
     }
     return RSV_OK;
 }
 
+template <typename R>
+rsv_status launch_traj_all(rsv_ctx* c, uint64_t sweep, const double* p0, float* acc_sum,
+                           float* acc_sq, void* h_prev_out) {
+    return launch_traj_tiles<R>(c, c->stream, 0, c->n_body + c->n_edge, sweep, p0, acc_sum,
+                                acc_sq, h_prev_out);
+}
+
 FinalizeArgs finalize_args(rsv_ctx* c, uint64_t sweep, int do_metropolis, int do_theta) {
     FinalizeArgs f;
     f.chains = c->chains;
+    f.chain_first = 0;
     f.n_chains = c->n_chains;
     f.partials = c->partials;
     f.chain_edge = c->edge;
@@ -623,9 +666,9 @@ size_t rsv_hmc_workspace_bytes(const rsv_problem* pb) {
     return L.total;
 }
 
-rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
-                        const float* log_mass, void* workspace, size_t ws_bytes,
-                        void* hip_stream) {
+static rsv_status init_impl(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
+                            const float* log_mass, void* workspace, size_t ws_bytes,
+                            void* hip_stream, bool two_streams) {
     if (!out) return fail(RSV_EINVAL, "out is NULL");
     *out = nullptr;
     Layout L;
@@ -717,6 +760,11 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
             return bail(fail(RSV_EINVAL, "chain %d: theta needs |phi| < 1, finite mu, xi and "
                                          "variances > 0", i));
     }
+    if (two_streams && c->n_chains >= 2) {
+        RSV_HIP_INIT(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        RSV_HIP_INIT(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        RSV_HIP_INIT(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
     // an initial decomposition so that the theta update works before any trajectory
     std::vector<rsv_leapfrog> lf0(pb->n_series, rsv_leapfrog{pb->max_steps, 0, 1.0});
     st = build_tiles(c, lf0.data());
@@ -724,6 +772,12 @@ rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta
 #undef RSV_HIP_INIT
     *out = c;
     return RSV_OK;
+}
+
+rsv_status rsv_hmc_init(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
+                        const float* log_mass, void* workspace, size_t ws_bytes,
+                        void* hip_stream) {
+    return init_impl(out, pb, h, theta, log_mass, workspace, ws_bytes, hip_stream, true);
 }
 
 rsv_status rsv_hmc_init_static(rsv_ctx** out, const rsv_problem* pb, void* h, rsv_theta* theta,
@@ -760,7 +814,7 @@ rsv_status rsv_hmc_init_static(rsv_ctx** out, const rsv_problem* pb, void* h, rs
         // on the device is refused even if this initialisation fails
         gen = ++g_static_gen[dev];
     }
-    st = rsv_hmc_init(out, pb, h, theta, log_mass, ws, RSV_STATIC_WORKSPACE_BYTES, hip_stream);
+    st = init_impl(out, pb, h, theta, log_mass, ws, RSV_STATIC_WORKSPACE_BYTES, hip_stream, false);
     if (st != RSV_OK) return st;
     (*out)->static_dev = dev;
     (*out)->static_gen = gen;
@@ -827,42 +881,103 @@ rsv_status rsv_hmc_sweep(rsv_ctx* c, uint64_t first_sweep, int32_t n_sweeps,
     float* acc_sq_f = c->acc_f + c->n_state;
     // without batch sums, the squares are flushed every 64 sweeps
     const int32_t bl = (trace && trace->h_batch_sum) ? trace->batch_len : 64;
+    // chain groups: two (on the context's stream and the side stream) unless
+    // there is one chain, a static context, or kernel timing records are on
+    // (each trajectory launch is then timed alone on the context's stream)
+    const int n_groups = (c->split < c->n_chains && c->ev_start.empty()) ? 2 : 1;
+    int32_t chain_lo[2] = {0, c->split}, chain_hi[2] = {c->split, c->n_chains};
+    int32_t tile_lo[2] = {c->group_tile_first[0], c->group_tile_first[1]};
+    int32_t tile_n[2] = {c->group_tiles[0], c->group_tiles[1]};
+    int64_t state_lo[2] = {0, 0}, state_n[2] = {c->n_state, 0};
+    if (n_groups == 2) {
+        state_lo[1] = c->h_chains[c->split].h_off;
+        state_n[0] = state_lo[1];
+        state_n[1] = c->n_state - state_lo[1];
+    } else {
+        chain_hi[0] = c->n_chains;
+        tile_lo[0] = 0;
+        tile_n[0] = c->n_body + c->n_edge;
+    }
+    hipStream_t gst[2] = {c->stream, c->side};
     auto batch_row = [&](int32_t i) -> double* {  // batch-sum row of the state after sweep i
         return trace->h_batch_sum
                    ? trace->h_batch_sum + static_cast<int64_t>(i / trace->batch_len) * c->n_state
                    : nullptr;
     };
-    auto flush = [&](int32_t i) -> hipError_t {  // end of the batch holding sweep i
-        return launch_flush(c->stream, c->n_state, acc_sum_f, acc_sq_f, batch_row(i),
-                            trace->h_sq_sum);
+    // end of the batch holding sweep i, for group g's states (or zeroing
+    // the FP32 buffers, without a row)
+    auto flush = [&](int g, double* row, double* sq) -> hipError_t {
+        return launch_flush(gst[g], state_n[g], acc_sum_f + state_lo[g], acc_sq_f + state_lo[g],
+                            row ? row + state_lo[g] : nullptr, sq ? sq + state_lo[g] : nullptr);
     };
-    if (acc && n_sweeps > 0)  // zero the FP32 buffers
-        RSV_HIP(launch_flush(c->stream, c->n_state, acc_sum_f, acc_sq_f, nullptr, nullptr));
-    for (int32_t i = 0; i < n_sweeps; ++i) {
-        const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;
-        double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
-        int32_t* ac = (trace && trace->accepted) ? trace->accepted + ofs : nullptr;
-        rsv_theta* tt = (trace && trace->theta) ? trace->theta + ofs : nullptr;
-        auto h_row = [&](int32_t r) -> void* {
-            return static_cast<char*>(trace->h) + static_cast<size_t>(r) * c->n_state * elem;
-        };
-        const bool rec_h = trace && trace->h;
-        // the trajectory of sweep i accumulates the state after sweep i - 1
-        // and writes it to that sweep's trace row; the last row is gathered
-        const bool add = acc && i > 0;
-        st = run_trajectory(c, first_sweep + static_cast<uint64_t>(i), nullptr, nullptr, dh, ac,
-                            update_theta ? 1 : 0, tt,
-                            rec_h && i == n_sweeps - 1 ? h_row(i) : nullptr, nullptr,
-                            add ? acc_sum_f : nullptr, add ? acc_sq_f : nullptr,
-                            rec_h && i > 0 ? h_row(i - 1) : nullptr);
-        if (st != RSV_OK) return st;
-        if (add && (i - 1) % bl == bl - 1) RSV_HIP(flush(i - 1));
+    if (n_groups == 2) {
+        RSV_HIP(hipEventRecord(c->ev_fork, c->stream));
+        RSV_HIP(hipStreamWaitEvent(c->side, c->ev_fork, 0));
     }
+    // the side stream's work is joined back into the context's stream on
+    // every way out, so that later calls see it finished
+    auto join = [&]() -> hipError_t {
+        if (n_groups < 2) return hipSuccess;
+        const hipError_t e = hipEventRecord(c->ev_join, c->side);
+        if (e != hipSuccess) return e;
+        return hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    };
+    auto body = [&]() -> rsv_status {
+        for (int g = 0; acc && n_sweeps > 0 && g < n_groups; ++g)
+            RSV_HIP(flush(g, nullptr, nullptr));
+        for (int32_t i = 0; i < n_sweeps; ++i) {
+            const uint64_t sweep = first_sweep + static_cast<uint64_t>(i);
+            const int64_t ofs = static_cast<int64_t>(i) * c->n_chains;
+            double* dh = (trace && trace->delta_h) ? trace->delta_h + ofs : nullptr;
+            int32_t* ac = (trace && trace->accepted) ? trace->accepted + ofs : nullptr;
+            rsv_theta* tt = (trace && trace->theta) ? trace->theta + ofs : nullptr;
+            // the trajectory of sweep i accumulates the state after sweep i - 1
+            // and writes it to that sweep's trace row; the last row is gathered
+            const bool add = acc && i > 0;
+            void* prev_row = (trace && trace->h && i > 0)
+                                 ? static_cast<char*>(trace->h) +
+                                       static_cast<size_t>(i - 1) * c->n_state * elem
+                                 : nullptr;
+            for (int g = 0; g < n_groups; ++g) {
+                const rsv_status st_g =
+                    c->pb.precision == RSV_F64
+                        ? launch_traj_tiles<double>(c, gst[g], tile_lo[g], tile_n[g], sweep,
+                                                    nullptr, add ? acc_sum_f : nullptr,
+                                                    add ? acc_sq_f : nullptr, prev_row)
+                        : launch_traj_tiles<float>(c, gst[g], tile_lo[g], tile_n[g], sweep,
+                                                   nullptr, add ? acc_sum_f : nullptr,
+                                                   add ? acc_sq_f : nullptr, prev_row);
+                if (st_g != RSV_OK) return st_g;
+                FinalizeArgs f = finalize_args(c, sweep, 1, update_theta ? 1 : 0);
+                f.chain_first = chain_lo[g];
+                f.n_chains = chain_hi[g] - chain_lo[g];
+                f.delta_h_out = dh;
+                f.accepted_out = ac;
+                f.theta_trace = tt;
+                RSV_HIP(launch_finalize(gst[g], f, c->max_tiles_per_chain));
+                if (add && (i - 1) % bl == bl - 1)
+                    RSV_HIP(flush(g, batch_row(i - 1), trace->h_sq_sum));
+            }
+        }
+        return RSV_OK;
+    };
+    const rsv_status st_body = body();
+    const hipError_t e_join = join();
+    if (st_body != RSV_OK) return st_body;
+    if (e_join != hipSuccess)
+        return fail(RSV_EDEVICE, "joining the side stream: %s", hipGetErrorString(e_join));
+    if (trace && trace->h && n_sweeps > 0)  // the state after the last sweep
+        RSV_HIP(launch_gather_state(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
+                                    c->h_prop, level_moves(c) ? c->shift : nullptr,
+                                    static_cast<char*>(trace->h) +
+                                        static_cast<size_t>(n_sweeps - 1) * c->n_state * elem,
+                                    c->pb.precision));
     if (acc && n_sweeps > 0) {  // the state after the last sweep, and its batch
         RSV_HIP(launch_accumulate(c->stream, c->chains, c->n_chains, c->max_T, c->accept, c->h,
                                   c->h_prop, level_moves(c) ? c->shift : nullptr, acc_sum_f,
                                   acc_sq_f, c->pb.precision));
-        RSV_HIP(flush(n_sweeps - 1));
+        RSV_HIP(launch_flush(c->stream, c->n_state, acc_sum_f, acc_sq_f, batch_row(n_sweeps - 1),
+                             trace->h_sq_sum));
     }
     return settle(c);
 }

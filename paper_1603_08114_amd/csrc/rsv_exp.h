@@ -62,6 +62,15 @@ __device__ __forceinline__ double exp_fast(double x) {
     return x < -745.1332191019412 ? 0.0 : hi;
 }
 
+// exp_fast with the clamp and saturation behind a branch on `sat`, which is
+// uniform over the wavefront (a real branch: the common case skips them).
+__device__ __forceinline__ double exp_dh(double x, bool sat) {
+    const double e = exp_fast<false>(x);
+    if (!sat) return e;
+    asm volatile("" ::: "memory");
+    return exp_fast<true>(x);
+}
+
 // e^x in FP64 for the leapfrog force only, shorter than exp_fast: ln2 is
 // taken as its FP64 value alone (n ln2 then carries |n| * 2.3e-17 of error),
 // P is the degree-9 minimax polynomial (relative error 1.4e-14), and n is
@@ -184,15 +193,12 @@ __device__ __forceinline__ void sincos_2pi_f32(float u, float& sn, float& cs) {
     cs = ((q + 1) & 2) ? -c_sel : c_sel;
 }
 
-// e^x in FP32: 2^h with h = x log2 e rounded, times e^r for the residual
-// r = x - h ln2 (formed exactly by one FMA), using 1 + r since |r| < 2^-20 |x|.
-__device__ __forceinline__ float exp_fast(float x) {
-    const float log2e = 0x1.715476p+0f;
-    const float ln2 = 0x1.62e430p-1f;
-    const float h = x * log2e;
-    const float r = __builtin_fmaf(-h, ln2, x);
-    const float e2 = __builtin_amdgcn_exp2f(h);
-    return __builtin_fmaf(e2, r, e2);
+// e^x in FP32 for the leapfrog force: 2^(x log2 e) by the hardware base-2
+// exponential.  Rounding x log2 e to FP32 changes the value by a relative
+// |x| 2^-24 or so, the same as rounding h itself to FP32 does; the force may
+// be any function of position (the chain stays exact, dH is formed in FP64).
+__device__ __forceinline__ float exp_force(float x) {
+    return __builtin_amdgcn_exp2f(x * 0x1.715476p+0f);
 }
 
 }  // namespace rsv

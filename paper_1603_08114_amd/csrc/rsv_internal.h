@@ -85,6 +85,7 @@ struct TrajArgs {
 
 struct FinalizeArgs {
     const ChainDesc* chains;
+    int32_t chain_first;        // a launch finalizes chains [chain_first, + n_chains)
     int32_t n_chains;
     const double* partials;
     const double* chain_edge;

@@ -36,7 +36,7 @@ __device__ inline R exp_neg(R x);
 template <>
 __device__ inline double exp_neg<double>(double x) { return exp_force(-x); }
 template <>
-__device__ inline float exp_neg<float>(float x) { return exp_fast(-x); }
+__device__ inline float exp_neg<float>(float x) { return exp_force(-x); }
 
 // Value of the current state at a site: the stored entry plus the chain's
 // pending level shift (0 unless level moves are on), rounded to the state's
@@ -101,17 +101,19 @@ struct DhSums {
 // has_next, the stationary prior of site 0 when first) and the site's
 // statistics.  h1 = h'_t, h0 = h_t, pj = p'_t, im = 1/m_t, yy = y_t^2,
 // rr = ln RV_t, h1n / h0n the next site's values.  Returns h1 - mu, h0 - mu.
-// SAT selects the saturating exponential; without it the caller has checked
-// |h0| <= 700 and |h0 - h1| <= 700 (same values in that range).
-template <bool RET, bool SAT>
+// sat (uniform over the wavefront) selects the saturating exponential;
+// without it the caller has checked |h0| <= 700 and |h0 - h1| <= 700, where
+// both give the same values.
+template <bool RET>
 __device__ __forceinline__ void dh_site(DhSums& D, double h1, double h0, double pj, double im,
                                         double yy, double rr, bool rv, bool has_next, double h1n,
                                         double h0n, bool first, double mu, double phi, double xi,
-                                        double inv_se, double inv_su, double& a1, double& a0) {
+                                        double inv_se, double inv_su, bool sat, double& a1,
+                                        double& a0) {
     double d = 0.5 * pj * pj * im;
     if (RET) {
-        const double ye0 = yy * exp_fast<SAT>(-h0);
-        const double x10 = exp_fast<SAT>(h0 - h1);  // e^{-h1} / e^{-h0}
+        const double ye0 = yy * exp_dh(-h0, sat);
+        const double x10 = exp_dh(h0 - h1, sat);  // e^{-h1} / e^{-h0}
         d += 0.5 * (h1 - h0) + 0.5 * ye0 * (x10 - 1.0);
         D.sy1 += ye0 * x10;
         D.sy0 += ye0;
@@ -475,44 +477,37 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
 
     DhSums D = {-kin0, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, 0.0, 0.0};
     double* edge = A.chain_edge + static_cast<int64_t>(td.chain) * kEdge;
-    auto dh_pass = [&](auto sat_c) {
-        constexpr bool SAT = decltype(sat_c)::value;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
-            if (t < td.a || t >= td.b) continue;
-            const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
-            const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
-            const double yy = RET ? (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) : 0.0;
-            const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + (j < S - 1)]);
-            const double h0n = (j == S - 1) ? h0_up : h0d[j + (j < S - 1)];
-            double a1, a0;
-            dh_site<RET, SAT>(D, static_cast<double>(h[j]), h0d[j], static_cast<double>(p[j]), im,
-                              yy, rr, rv, t + 1 < T, h1n, h0n, t == 0, mu, phi, xi, inv_se,
-                              inv_su, a1, a0);
-            if (t == 0) {
-                edge[0] = a1;
-                edge[2] = a0;
-            }
-            if (t == T - 1) {
-                edge[1] = a1;
-                edge[3] = a0;
-            }
-            hp[t] = h[j];
-        }
-    };
     // the exponentials of the pass saturate only where an argument may leave
-    // [-700, 700] (a diverged proposal, or NaN): one uniform branch per wavefront
+    // [-700, 700] (a diverged proposal, or NaN): a uniform branch per wavefront
     bool in_range = true;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const double h1j = static_cast<double>(h[j]);
         in_range = in_range && __builtin_fabs(h0d[j]) <= 700.0 && __builtin_fabs(h0d[j] - h1j) <= 700.0;
     }
-    if (__ballot(!in_range) == 0)
-        dh_pass(std::false_type{});
-    else
-        dh_pass(std::true_type{});
+    const bool sat = __ballot(!in_range) != 0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int t = t0 + j;
+        if (t < td.a || t >= td.b) continue;
+        const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
+        const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
+        const double yy = RET ? (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) : 0.0;
+        const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + (j < S - 1)]);
+        const double h0n = (j == S - 1) ? h0_up : h0d[j + (j < S - 1)];
+        double a1, a0;
+        dh_site<RET>(D, static_cast<double>(h[j]), h0d[j], static_cast<double>(p[j]), im, yy, rr,
+                     rv, t + 1 < T, h1n, h0n, t == 0, mu, phi, xi, inv_se, inv_su, sat, a1, a0);
+        if (t == 0) {
+            edge[0] = a1;
+            edge[2] = a0;
+        }
+        if (t == T - 1) {
+            edge[1] = a1;
+            edge[3] = a0;
+        }
+        hp[t] = h[j];
+    }
 
     double red[kNQ];
     red[kPartDH] = D.dH;
@@ -1078,7 +1073,7 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     __shared__ Comp part[NT / kWave][kNQ];
     __shared__ ThetaDraws draws;
     __shared__ int last;
-    const int c = blockIdx.y;
+    const int c = A.chain_first + static_cast<int>(blockIdx.y);
     const int sl = blockIdx.x;
     const ChainDesc cd = A.chains[c];
     const int n_sl = (cd.tile_count + kSliceTiles - 1) / kSliceTiles;
@@ -1153,7 +1148,7 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
 __global__ __launch_bounds__(2 * kWave) void k_finalize(FinalizeArgs A) {
     __shared__ Comp part[1][kNQ];
     __shared__ ThetaDraws draws;
-    const int c = blockIdx.x;
+    const int c = A.chain_first + static_cast<int>(blockIdx.x);
     if (threadIdx.x >= kWave) {
         finalize_draws(A, c, A.chains[c].T, threadIdx.x - kWave, kWave, draws);
         __syncthreads();  // meets the first wavefront's barrier before the decision

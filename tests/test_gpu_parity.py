@@ -407,6 +407,34 @@ def test_sweep_is_deterministic():
     assert torch.equal(oa["theta"], ob["theta"])
 
 
+@pytest.mark.parametrize("precision", [RSV_F64, RSV_F32_MIXED])
+def test_two_stream_sweeps_equal_one_stream_sweeps(precision):
+    """A context made by rsv_hmc_init runs the chains of rsv_hmc_sweep in two
+    groups on two streams; a static context (rsv_hmc_init_static) runs them
+    on its one stream.  Every output is the same bit for bit: h after every
+    sweep, dH, decisions, theta, and the batch sums of h and h^2."""
+    Ts, C, k, dt = [1000, 37, 2048, 1501, 700], 3, 20, 0.05
+    offsets, ys, rs, hs = make_series(Ts, 41)
+    h0 = state_from(hs, C, 0.05)
+    th = [TH for _ in range(len(Ts) * C)]
+    outs = []
+    for static in (True, False):
+        smp = api.RSVSampler(offsets, np.concatenate(ys), np.concatenate(rs), h0, th,
+                             chains_per_series=C, precision=precision, max_steps=k, seed=9,
+                             static_workspace=static)
+        a = smp.sweep(0, 9, (k, dt), record=("delta_h", "accepted", "theta"), record_h=True)
+        b = smp.sweep(9, 10, (k, dt), record=("accepted",), batch_len=4)
+        outs.append((a, b, smp.h.clone(), smp.theta.clone()))
+        smp.close()
+    (a1, b1, h1, t1), (a2, b2, h2, t2) = outs
+    for key in a1:
+        assert torch.equal(a1[key], a2[key]), key
+    for key in b1:
+        assert torch.equal(b1[key], b2[key]), key
+    assert torch.equal(h1, h2) and torch.equal(t1, t2)
+    assert bool(a1["accepted"].any())
+
+
 @pytest.mark.parametrize("terms", [3, 1])
 def test_f32_mixed_trajectory_error_vs_f64(terms):
     """FP32 leapfrog, FP64 dH: error against the FP64 oracle on identical
