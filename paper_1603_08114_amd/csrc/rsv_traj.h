@@ -202,10 +202,13 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const R db = static_cast<R>(dk * beta);
     const R mu_r = static_cast<R>(mu), phi_r = static_cast<R>(phi);
 
-    // with a diagonal mass: sqrt(m_t) per site (read with the state, so that
-    // its latency overlaps the momentum draw, and kept for the dH pass) and
-    // the per-site drift step dt / m_t
+    // The loads of the tile's inputs are issued first and consumed after the
+    // momentum draw, which needs none of them, so that their latency overlaps
+    // it: the state h, the data (y^2, ln RV), with a diagonal mass sqrt(m_t)
+    // (kept for the dH pass), and the batch-means accumulators.
     R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1], msq[MASS ? S : 1];
+    R y_in[S], r_in[S];
+    float acc_s[S], acc_q[S];
     double kin0 = 0.0;  // kinetic energy of the exact sites at the start
 
     const bool in_b = A.state_sel[td.chain] != 0;
@@ -221,8 +224,52 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const bool live = t < T;
         h[j] = live ? state_at(hc, t, shift) : R(0);
         if constexpr (MASS) msq[j] = live ? msq_tab[t] : R(1);
-        const double yy = live ? static_cast<double>(y2[t]) : 0.0;
-        const double rr = live ? static_cast<double>(lr[t]) : 0.0;
+        y_in[j] = live ? y2[t] : R(0);
+        r_in[j] = live ? lr[t] : R(0);
+    }
+    // batch-means accumulators of the starting state (the previous sweep's
+    // result) on the exact sites, read here and written back below
+    if (A.acc_sum || A.acc_sq) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            const int64_t i = cd.h_off + t;
+            const bool ex = t >= td.a && t < td.b;
+            acc_s[j] = (ex && A.acc_sum) ? A.acc_sum[i] : 0.0f;
+            acc_q[j] = (ex && A.acc_sq) ? A.acc_sq[i] : 0.0f;
+        }
+    }
+
+    // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
+    // (the factor sqrt(m_t) is applied below, once the table has arrived)
+    if (A.p0) {
+        const double* p0 = A.p0 + cd.h_off;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            p[j] = (t < T) ? static_cast<R>(p0[t]) : R(0);
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < S / 4; ++g) {
+            R z[4];
+            momentum_normals<R>(A.seed, static_cast<uint64_t>((t0 >> 2) + g), A.sweep,
+                                static_cast<uint64_t>(td.chain), z);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) p[4 * g + q] = z[q];
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            R pm = p[j];
+            if constexpr (MASS) pm *= msq[MASS ? j : 0];
+            p[j] = (t0 + j < T) ? pm : R(0);
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const double yy = static_cast<double>(y_in[j]);
+        const double rr = static_cast<double>(r_in[j]);
         dc[j] = static_cast<R>(-dk * (c_base - rr * inv_su));
         ds[j] = RET ? static_cast<R>(0.5 * dk * yy) : R(0);
         if constexpr (STAGE) {
@@ -244,10 +291,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const uint64_t any_bad = __ballot(bad);
         if (any_bad != 0 && lane == 0) atomicOr(&A.counters[kCntNonfiniteState], 1u);
     }
-    // batch-means accumulators of the starting state (the previous sweep's
-    // result) on the exact sites: the read-modify-writes overlap with the
-    // momentum draw instead of costing a separate pass over the state
-    // (and the trace row of the previous sweep, the same values)
+    // the accumulators and the trace row of the previous sweep (the same values)
     if (A.acc_sum || A.acc_sq || A.h_prev_out) {
 #pragma unroll
         for (int j = 0; j < S; ++j) {
@@ -255,34 +299,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             if (t >= td.a && t < td.b) {
                 const float v = static_cast<float>(h[j]);
                 const int64_t i = cd.h_off + t;
-                if (A.acc_sum) A.acc_sum[i] += v;
-                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, A.acc_sq[i]);
+                if (A.acc_sum) A.acc_sum[i] = acc_s[j] + v;
+                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, acc_q[j]);
                 if (A.h_prev_out) A.h_prev_out[i] = h[j];
-            }
-        }
-    }
-
-    // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
-    if (A.p0) {
-        const double* p0 = A.p0 + cd.h_off;
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
-            p[j] = (t < T) ? static_cast<R>(p0[t]) : R(0);
-        }
-    } else {
-#pragma unroll
-        for (int g = 0; g < S / 4; ++g) {
-            R z[4];
-            momentum_normals<R>(A.seed, static_cast<uint64_t>((t0 >> 2) + g), A.sweep,
-                                static_cast<uint64_t>(td.chain), z);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int j = 4 * g + q;
-                const int t = t0 + j;
-                R pm = z[q];
-                if constexpr (MASS) pm *= msq[MASS ? j : 0];
-                p[j] = (t < T) ? pm : R(0);
             }
         }
     }
