@@ -252,10 +252,12 @@ rsv_status rsv_hmc_init_static(rsv_ctx **out, const rsv_problem *pb, void *h, rs
 /* Momentum refresh of sweep `sweep` (the Gibbs draw p ~ N(0, m) implied by
  * the kinetic term of H, Sec. 3), written to p_out (device, FP64, one entry
  * per state entry).  The trajectory of that sweep starts from exactly these
- * momenta.  Site t of a chain takes normal t%4 of Philox block t/4 (Box-Muller
- * on the block's two pairs of uniforms).  On the FP32-mixed path the normals
- * and the product with sqrt(m_t) are formed in FP32 from the same uniforms,
- * so the values are FP32 numbers within a few FP32 ulps of the FP64 path's. */
+ * momenta.  FP64: site t of a chain takes normal t%4 of Philox block t/4
+ * (Box-Muller on the block's two pairs of 52-bit uniforms).  FP32-mixed:
+ * site t takes normal t%8 of block t/8; word q of the block gives sites 2q
+ * and 2q+1 by Box-Muller on u0 from its top 40 bits and u1 from its low 24,
+ * formed in FP32 (as is the product with sqrt(m_t)), so the values are FP32
+ * numbers. */
 rsv_status rsv_hmc_momenta(rsv_ctx *c, uint64_t sweep, double *p_out);
 
 /* One HMC trajectory for every chain (Sec. 3): momentum refresh, k leapfrog

@@ -64,6 +64,7 @@ def _load():
                                    C.c_double]),
         "orc_delta_h": (C.c_double, [_I64, _D, _D, _D, _D, _D, _D, _D, P(Theta), C.c_int]),
         "orc_momenta": (None, [_U64, _U64, _U64, _I64, _D, _D]),
+        "orc_momenta_f32": (None, [_U64, _U64, _U64, _I64, _D, _D]),
         "orc_log_u": (C.c_double, [_U64, _U64, _U64]),
         "orc_trajectory": (C.c_int, [_I64, _D, _D, _D, _D, P(Theta), C.c_int, C.c_int32,
                                      C.c_double, C.c_int, _U64, _U64, _U64, _D, _D, _D, _D]),
@@ -219,6 +220,14 @@ def momenta(seed, sweep, chain, T, log_m=None):
     p = np.zeros(T)
     lm = None if log_m is None else _arr(log_m, T)
     _lib.orc_momenta(seed, sweep, chain, T, _ptr(lm), _ptr(p))
+    return p
+
+
+def momenta_f32(seed, sweep, chain, T, log_m=None):
+    """Momenta of the FP32-mixed path's stream layout, in FP64."""
+    p = np.zeros(T)
+    lm = None if log_m is None else _arr(log_m, T)
+    _lib.orc_momenta_f32(seed, sweep, chain, T, _ptr(lm), _ptr(p))
     return p
 
 

@@ -321,6 +321,29 @@ void orc_momenta(uint64_t seed, uint64_t sweep, uint64_t chain, int64_t T,
     }
 }
 
+/* Momentum refresh of the FP32-mixed path (the library's own stream layout
+ * for that precision): site t takes normal t%8 of Philox block t/8 of the
+ * momentum stream; word q of the block gives sites 2q and 2q+1 of the block
+ * by Box-Muller on u0 = (top 40 bits + 1/2) 2^-40 and u1 = (low 24 bits +
+ * 1/2) 2^-24.  Computed here in FP64; the library forms it in FP32. */
+void orc_momenta_f32(uint64_t seed, uint64_t sweep, uint64_t chain, int64_t T,
+                     const double *log_m, double *p)
+{
+    for (int64_t t = 0; t < T; ++t) {
+        uint64_t ctr[4] = { (uint64_t)(t / 8), sweep, chain, ORC_TAG_MOMENTUM };
+        uint64_t key[2] = { seed, 0 };
+        uint64_t w[4];
+        orc_philox4x64_10(ctr, key, w);
+        const int r = (int)(t % 8);
+        const uint64_t word = w[r / 2];
+        const double u0 = ((double)(word >> 24) + 0.5) * 0x1p-40;
+        const double u1 = ((double)(word & 0xFFFFFFu) + 0.5) * 0x1p-24;
+        double z0, z1;
+        box_muller(u0, u1, &z0, &z1);
+        p[t] = ((r & 1) ? z1 : z0) * (log_m ? exp(0.5 * log_m[t]) : 1.0);
+    }
+}
+
 double orc_log_u(uint64_t seed, uint64_t sweep, uint64_t chain)
 {
     double u[4];

@@ -100,6 +100,9 @@ double orc_delta_h(int64_t T, const double *h0, const double *p0,
 /* Momentum refresh p_t ~ N(0, m_t) for (seed, sweep, chain). */
 void orc_momenta(uint64_t seed, uint64_t sweep, uint64_t chain, int64_t T,
                  const double *log_m, double *p);
+/* The same on the FP32-mixed path's stream layout (8 sites per block). */
+void orc_momenta_f32(uint64_t seed, uint64_t sweep, uint64_t chain, int64_t T,
+                     const double *log_m, double *p);
 /* log u of the Metropolis test of (seed, sweep, chain). */
 double orc_log_u(uint64_t seed, uint64_t sweep, uint64_t chain);
 

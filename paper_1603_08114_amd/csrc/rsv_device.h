@@ -87,34 +87,51 @@ __device__ inline void gauss_pair(double u0, double u1, double& z0, double& z1) 
     z1 = radius * s;
 }
 
-// Box-Muller in FP32, for momenta of the FP32-mixed path: the same uniforms
-// as gauss_pair, rounded to FP32 (u0 keeps its full range, so the tail of
-// the radius does too), the radius from the hardware base-2 logarithm and
-// square root (sqrt(-2 ln2 log2 u0)), the angle by sincos_2pi_f32.  The
-// normals agree with gauss_pair's to a few FP32 ulps.
-__device__ inline void gauss_pair_f32(double u0, double u1, float& z0, float& z1) {
-    const float l2 = __builtin_amdgcn_logf(static_cast<float>(u0));
+// Box-Muller in FP32 on one pair of uniforms: the radius from the hardware
+// base-2 logarithm and square root (sqrt(-2 ln2 log2 u0)), the angle by
+// sincos_2pi_f32.
+__device__ inline void gauss_pair_f32(float u0, float u1, float& z0, float& z1) {
+    const float l2 = __builtin_amdgcn_logf(u0);
     const float radius = __builtin_amdgcn_sqrtf(-1.38629436112f * l2);
     float s, c;
-    sincos_2pi_f32(static_cast<float>(u1), s, c);
+    sincos_2pi_f32(u1, s, c);
     z0 = radius * c;
     z1 = radius * s;
 }
 
-// Momentum normals of block idx (sites 4 idx .. 4 idx + 3) of a chain's
-// stream, in the path's precision: FP64 by gauss_pair, FP32 by
-// gauss_pair_f32.  The trajectory kernel and rsv_hmc_momenta both draw here.
+// Momentum normals of one Philox block of a chain's momentum stream, in the
+// path's precision.  FP64: block idx holds sites 4 idx .. 4 idx + 3, the
+// normals of gauss_pair on the block's four 52-bit uniforms.  FP32-mixed:
+// block idx holds sites 8 idx .. 8 idx + 7; word q gives sites 8 idx + 2q
+// and + 2q + 1 by Box-Muller in FP32 on u0 from its top 40 bits and u1 from
+// its low 24 (each centred in its cell, u0 rounded to FP32).  The trajectory
+// kernel and rsv_hmc_momenta both draw here.
+template <typename R>
+constexpr int kMomentumBlock = sizeof(R) == sizeof(double) ? 4 : 8;
+
 template <typename R>
 __device__ inline void momentum_normals(uint64_t seed, uint64_t idx, uint64_t sweep,
-                                        uint64_t chain, R z[4]) {
-    double u[4];
-    uniforms4(seed, idx, sweep, chain, kTagMomentum, u);
+                                        uint64_t chain, R (&z)[kMomentumBlock<R>]) {
     if constexpr (sizeof(R) == sizeof(double)) {
+        double u[4];
+        uniforms4(seed, idx, sweep, chain, kTagMomentum, u);
         gauss_pair(u[0], u[1], z[0], z[1]);
         gauss_pair(u[2], u[3], z[2], z[3]);
     } else {
-        gauss_pair_f32(u[0], u[1], z[0], z[1]);
-        gauss_pair_f32(u[2], u[3], z[2], z[3]);
+        const Philox4x64 x = Philox4x64::encrypt(idx, sweep, chain, kTagMomentum, seed, 0ull);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t w = x.w[q];
+            const uint32_t top = static_cast<uint32_t>(w >> 32);
+            const uint32_t mid = static_cast<uint32_t>(w >> 24) & 0xFFu;
+            const uint32_t low = static_cast<uint32_t>(w) & 0xFFFFFFu;
+            // ((w >> 24) + 1/2) 2^-40 and ((w & 0xFFFFFF) + 1/2) 2^-24
+            const float u0 = __builtin_fmaf(static_cast<float>(top), 0x1p-32f,
+                                            __builtin_fmaf(static_cast<float>(mid), 0x1p-40f,
+                                                           0x1p-41f));
+            const float u1 = __builtin_fmaf(static_cast<float>(low), 0x1p-24f, 0x1p-25f);
+            gauss_pair_f32(u0, u1, z[2 * q], z[2 * q + 1]);
+        }
     }
 }
 

@@ -113,15 +113,16 @@ __global__ __launch_bounds__(256) void k_mass_table(const float* log_mass, int64
 template <typename M>
 __global__ __launch_bounds__(256) void k_momenta(const ChainDesc* chains, const M* mass_sqrt,
                                                  uint64_t seed, uint64_t sweep, double* p_out) {
+    constexpr int NB = kMomentumBlock<M>;
     const int c = blockIdx.y;
     const ChainDesc cd = chains[c];
-    const int n_blocks = (cd.T + 3) / 4;
+    const int n_blocks = (cd.T + NB - 1) / NB;
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n_blocks;
          g += gridDim.x * blockDim.x) {
-        M z[4];
+        M z[NB];
         momentum_normals<M>(seed, static_cast<uint64_t>(g), sweep, static_cast<uint64_t>(c), z);
-        for (int q = 0; q < 4; ++q) {
-            const int t = 4 * g + q;
+        for (int q = 0; q < NB; ++q) {
+            const int t = NB * g + q;
             if (t >= cd.T) break;
             const M pm = mass_sqrt ? z[q] * mass_sqrt[cd.d_off + t] : z[q];
             p_out[cd.h_off + t] = static_cast<double>(pm);

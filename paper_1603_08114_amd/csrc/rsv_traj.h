@@ -240,8 +240,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
-    // momentum refresh p ~ N(0, m): site t takes normal t%4 of block t/4
-    // (the factor sqrt(m_t) is applied below, once the table has arrived)
+    // momentum refresh p ~ N(0, m): site t takes normal t%NB of block t/NB
+    // (NB = 4 in FP64, 8 in FP32; tiles start at multiples of 8); the factor
+    // sqrt(m_t) is applied below, once the table has arrived
     if (A.p0) {
         const double* p0 = A.p0 + cd.h_off;
 #pragma unroll
@@ -250,13 +251,15 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             p[j] = (t < T) ? static_cast<R>(p0[t]) : R(0);
         }
     } else {
+        constexpr int NB = kMomentumBlock<R>;
+        static_assert(S % NB == 0, "lanes hold whole Philox blocks");
 #pragma unroll
-        for (int g = 0; g < S / 4; ++g) {
-            R z[4];
-            momentum_normals<R>(A.seed, static_cast<uint64_t>((t0 >> 2) + g), A.sweep,
+        for (int g = 0; g < S / NB; ++g) {
+            R z[NB];
+            momentum_normals<R>(A.seed, static_cast<uint64_t>(t0 / NB + g), A.sweep,
                                 static_cast<uint64_t>(td.chain), z);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) p[4 * g + q] = z[q];
+            for (int q = 0; q < NB; ++q) p[NB * g + q] = z[q];
         }
 #pragma unroll
         for (int j = 0; j < S; ++j) {

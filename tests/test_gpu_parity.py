@@ -118,11 +118,12 @@ def test_momenta_with_mass():
 
 @pytest.mark.parametrize("mass", [False, True])
 def test_f32_momenta_are_the_streams_in_fp32(mass):
-    """On the FP32-mixed path the momenta come from the same uniforms through
-    an FP32 Box-Muller: rsv_hmc_momenta returns FP32 values that agree with
-    the oracle's FP64 normals (times sqrt(m_t)) to a few FP32 ulps, and a
-    trajectory on the context's own streams equals, bit for bit, the one
-    from those momenta injected (the kernel draws exactly these)."""
+    """On the FP32-mixed path the momenta take eight sites per Philox block
+    and an FP32 Box-Muller: rsv_hmc_momenta returns FP32 values that agree
+    with the oracle's FP64 evaluation of that layout (times sqrt(m_t)) to a
+    few FP32 ulps, and a trajectory on the context's own streams equals, bit
+    for bit, the one from those momenta injected (the kernel draws exactly
+    these)."""
     Ts, C, k, dt = [700, 3000, 64], 2, 20, 0.05
     n = int(np.sum(Ts))
     lm = (0.4 * np.sin(np.arange(n) * 0.03)).astype(np.float32) if mass else None
@@ -136,7 +137,7 @@ def test_f32_momenta_are_the_streams_in_fp32(mass):
     for c, (s, sl) in enumerate(chain_slices(offsets, C)):
         T = sl.stop - sl.start
         lms = None if lm is None else lm[offsets[s]:offsets[s + 1]].astype(np.float64)
-        ref = oracle.momenta(smp.pb.seed, 11, c, T, log_m=lms)
+        ref = oracle.momenta_f32(smp.pb.seed, 11, c, T, log_m=lms)
         np.testing.assert_allclose(p[sl], ref, rtol=4e-6, atol=4e-6)
     log_u = np.log(np.random.default_rng(3).uniform(size=smp.n_chains))
     dh_a, acc_a = smp.trajectory(11, (k, dt), log_u=log_u)

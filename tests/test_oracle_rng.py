@@ -67,6 +67,25 @@ def test_normals_ks_and_moments():
     assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < 4 / np.sqrt(n / 2)
 
 
+def test_fp32_path_momenta_law():
+    """The FP32-mixed path's layout (8 sites per Philox block, u0 from 40
+    bits, u1 from 24): N(0, 1) by KS, mean, variance and kurtosis; the two
+    normals of a pair uncorrelated, and so are neighbouring blocks; every
+    radius within sqrt(-2 ln 2^-41), the smallest u0; and a stream apart
+    from the FP64 layout's."""
+    z = oracle.momenta_f32(seed=5, sweep=2, chain=3, T=400_000)
+    n = z.size
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 4 / np.sqrt(n)
+    assert abs(z.var() - 1.0) < 4 * np.sqrt(2.0 / n)
+    assert abs(stats.kurtosis(z, fisher=False) - 3.0) < 6 * np.sqrt(24.0 / n)
+    assert abs(np.corrcoef(z[0::2], z[1::2])[0, 1]) < 4 / np.sqrt(n / 2)
+    blocks = z.reshape(-1, 8)
+    assert abs(np.corrcoef(blocks[:-1, 0], blocks[1:, 0])[0, 1]) < 4 / np.sqrt(blocks.shape[0])
+    assert np.max(np.abs(z)) <= np.sqrt(2.0 * 41 * np.log(2.0))
+    assert not np.allclose(z[:64], oracle.momenta(5, 2, 3, 64))
+
+
 def test_streams_are_distinct():
     a = oracle.normal_stream(1, 0, 0, 0, 64)
     for (sw, ch, tag) in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]:
