@@ -350,8 +350,8 @@ def batched_data(S_=512, C_=4):
 
 
 def batched_arm(data, k, jit, level, omelyan=False, shape=None, n=2000, bl=40,
-                precision=None, terms=None):
-    """Warm-up of 500 sweeps with dtau adapted per series to acceptance 0.8
+                precision=None, terms=None, warm=500):
+    """Warm-up of `warm` (500) sweeps with dtau adapted per series to acceptance 0.8
     (stochastic approximation on ln dtau, windows of 25 sweeps), then n
     measured sweeps with batch means accumulated on the device; min over
     {h_t} and theta of the ESS of each series (its chains summed), per second
@@ -380,7 +380,7 @@ def batched_arm(data, k, jit, level, omelyan=False, shape=None, n=2000, bl=40,
         S_t, NW_t = shape
     smp = api.RSVSampler(off, data["y"], data["log_rv"], data["h0"], data["theta0"], max_steps=k_,
                          seed=3, sites_per_lane=S_t, waves_per_tile=NW_t, **kw)
-    dtau, sweep, _, _ = LM.adapt(smp, k_, dtau, 0, 500, S_, C_, update_theta=True)
+    dtau, sweep, _, _ = LM.adapt(smp, k_, dtau, 0, warm, S_, C_, update_theta=True)
     lf = [(k_, d) for d in dtau]
     smp.sweep(sweep, 1, lf, update_theta=True, record=())  # apply the final decomposition
     sweep += 1
@@ -433,12 +433,26 @@ def run_batched(args):
     (50 batches of 40) accumulated on the device.  value = median over series
     of min-ESS/s under the paper's sampler (fixed dtau, Gibbs theta); beside
     it the extensions: step-size jitter 0.5 with the level move, and
-    Omelyan's integrator at the same 30 force evaluations."""
+    Omelyan's integrator at the same 30 force evaluations.  With --steps below
+    200 (a short run for counter collection): that many measured sweeps after
+    50 warm-up sweeps, the paper's sampler only, and the tile shape of
+    --sites-per-lane / --waves-per-tile when given."""
     k = 30
     data = batched_data()
     Ts = np.diff(data["offsets"])
     jit = jitter_of(args, 0.0)
     level = level_of(args, False)
+    if args.steps < 200:
+        shape = (args.sites_per_lane, args.waves_per_tile) if args.sites_per_lane else None
+        arm = batched_arm(data, k, jit, level, shape=shape, n=args.steps, bl=1, warm=50)
+        return {"metric": METRIC, "value": arm["median"], "unit": "min-ESS/s (median over series)",
+                "n_gpus": 1, "steps": arm["n"], "warmup": 50, "ms_per_step": arm["ms_per_sweep"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32-mixed", "data": "synthetic (RSV model eqs. (1)-(3), seeded)",
+                "config": {"workload": f"batched RSV HMC, short run of {arm['n']} sweeps (counter "
+                                       "collection; ESS from so few sweeps is not meaningful)",
+                           "sites_per_lane": arm["S"], "waves_per_tile": arm["NW"]},
+                "site_updates_per_s": arm["site_updates_per_s"]}
     main_arm = batched_arm(data, k, jit, level)
     ext = batched_arm(data, k, 0.5, True, shape=(main_arm["S"], main_arm["NW"]))
     om = batched_arm(data, k, 0.5, True, omelyan=True)
