@@ -25,6 +25,13 @@
  *     rsv_hmc_check synchronise; rsv_hmc_momenta, rsv_hmc_trajectory,
  *     rsv_theta_update and rsv_hmc_sweep first wait for the work already on
  *     the stream and read the non-finite flag (below), then only enqueue.
+ *     A context of rsv_hmc_init with two or more chains also owns a side
+ *     stream (default priority) and two events, made at init and destroyed
+ *     by rsv_hmc_destroy: rsv_hmc_sweep runs about half of the chains there,
+ *     forked from the given stream by an event at the start of the call and
+ *     joined back into it by another at its end, so the call's work is
+ *     ordered on the given stream as a whole.  Results are the same as on
+ *     one stream, bit for bit.
  *   - A non-OK status leaves the context usable; rsv_last_error() returns a
  *     thread-local message describing the most recent failure.
  *   - Non-finite state.  The trajectory kernel flags a non-finite value in
