@@ -219,6 +219,7 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     // (kept for the dH pass), and the batch-means accumulators.
     R h[S], p[S], dc[S], ds[S], dtm[MASS ? S : 1], msq[MASS ? S : 1];
     R y_in[S], r_in[S];
+    R acc_h[S];
     float acc_s[S], acc_q[S];
     double kin0 = 0.0;  // kinetic energy of the exact sites at the start
 
@@ -239,15 +240,23 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         r_in[j] = live ? lr[t] : R(0);
     }
     // batch-means accumulators of the starting state (the previous sweep's
-    // result) on the exact sites, read here and written back below
-    if (A.acc_sum || A.acc_sq) {
+    // result) and the trace row of the previous sweep, on the exact sites,
+    // read here and written back below.  They need no per-lane order, so the
+    // wavefront covers its block of 64 S sites in coalesced rounds (round r:
+    // site wbase + 64 r + lane) instead of each lane's S neighbouring sites
+    // (addresses S elements apart across lanes, which cost the memory pipeline
+    // several times more per element); the state values are read again the same way.
+    const int wbase = td.la + wv * kWave * S;
+    const bool acc_on = A.acc_sum || A.acc_sq || A.h_prev_out;
+    if (acc_on) {
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
+        for (int r = 0; r < S; ++r) {
+            const int t = wbase + r * kWave + lane;
             const int64_t i = cd.h_off + t;
             const bool ex = t >= td.a && t < td.b;
-            acc_s[j] = (ex && A.acc_sum) ? A.acc_sum[i] : 0.0f;
-            acc_q[j] = (ex && A.acc_sq) ? A.acc_sq[i] : 0.0f;
+            acc_h[r] = ex ? state_at(hc, t, shift) : R(0);
+            acc_s[r] = (ex && A.acc_sum) ? A.acc_sum[i] : 0.0f;
+            acc_q[r] = (ex && A.acc_sq) ? A.acc_sq[i] : 0.0f;
         }
     }
 
@@ -306,16 +315,16 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         if (any_bad != 0 && lane == 0) atomicOr(&A.counters[kCntNonfiniteState], 1u);
     }
     // the accumulators and the trace row of the previous sweep (the same values)
-    if (A.acc_sum || A.acc_sq || A.h_prev_out) {
+    if (acc_on) {
 #pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int t = t0 + j;
+        for (int r = 0; r < S; ++r) {
+            const int t = wbase + r * kWave + lane;
             if (t >= td.a && t < td.b) {
-                const float v = static_cast<float>(h[j]);
+                const float v = static_cast<float>(acc_h[r]);
                 const int64_t i = cd.h_off + t;
-                if (A.acc_sum) A.acc_sum[i] = acc_s[j] + v;
-                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, acc_q[j]);
-                if (A.h_prev_out) A.h_prev_out[i] = h[j];
+                if (A.acc_sum) A.acc_sum[i] = acc_s[r] + v;
+                if (A.acc_sq) A.acc_sq[i] = __builtin_fmaf(v, v, acc_q[r]);
+                if (A.h_prev_out) A.h_prev_out[i] = acc_h[r];
             }
         }
     }
