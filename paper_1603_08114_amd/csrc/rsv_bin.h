@@ -40,7 +40,7 @@ __global__ __launch_bounds__(NW == 1 ? 256 : 64 * NW) void k_bin(BinArgs<R> B) {
     constexpr int kWaves = NW == 1 ? 4 : NW;
     using St = Stage<R, S, NW, kTPB>;
     __shared__ TileShared<R, NW> tsh[kTPB];
-    __shared__ double stage_all[kTPB][St::n];
+    __shared__ R stage_all[kTPB][St::n];
     __shared__ Comp part[kWaves][1][kNQ];
     __shared__ ThetaDraws draws[kWaves];
 

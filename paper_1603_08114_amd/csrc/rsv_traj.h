@@ -164,16 +164,32 @@ struct TileShared {
     double up1[NW], up0[NW];
 };
 
-// FP64 tiles keep the starting h, y^2 and ln RV of their sites in LDS for
-// the dH pass after the leapfrog loop (laid out [quantity][site j][lane],
-// each lane reading back only what it wrote), so that pass does not re-read
-// them from memory: the tiles in flight on one XCD hold more than its L2.
-// Enabled while a block's copy fits 48 KB (S * NW * tiles per block <= 32).
+// The tile's starting h, y^2 and ln RV pass through LDS (laid out
+// [quantity][site j][lane], rows padded by one element): the wavefront reads
+// its block of 64 S sites from memory in coalesced rounds (round r: site
+// base + 64 r + lane) and scatters them to their owners' slots, and each lane
+// then reads its S sites.  Reading each lane's S neighbouring sites directly
+// puts addresses S elements apart across the lanes of one load, which costs
+// the memory pipeline several times more per element.  FP64 tiles keep the
+// values there for the dH pass after the leapfrog loop (so it does not
+// re-read them: the tiles in flight on one XCD hold more than its L2); the
+// FP32 dH pass reads h0 from there and the FP64 data from memory.  On for
+// every FP32 shape (at most 50 KB per block) and for FP64 while a block's
+// copy stays under 51 KB (S * NW * tiles per block <= 32).
 template <typename R, int S, int NW, int TPB>
 struct Stage {
-    static constexpr bool on = sizeof(R) == sizeof(double) && S * NW * TPB <= 32;
-    static constexpr int n = on ? 3 * S * 64 * NW : 1;
+    static constexpr bool on = sizeof(R) == sizeof(float) || S * NW * TPB <= 32;
+    static constexpr int row = 64 * NW + 1;  // a quantity's row of one site j
+    static constexpr int n = on ? 3 * S * row : 1;
 };
+
+// Orders a wavefront's LDS writes before its reads of other lanes' slots
+// (the slots written and read belong to this wavefront only).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // 1/m_t from the stored sqrt(m_t), in FP64 with a correctly rounded division:
 // the momentum is drawn as z sqrt(m_t), so the kinetic term p^2 / (2 m_t)
@@ -188,7 +204,7 @@ __device__ __forceinline__ double inv_mass(R sqrt_m) {
 template <typename R, int S, int NW, bool MASS, bool EDGE, bool RET, bool STAGE>
 __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW>& sh,
                                           const int tile_id, const int wv, const int lane,
-                                          double* stage) {
+                                          R* stage) {
     const TileDesc td = A.tiles[tile_id];
     const ChainDesc cd = A.chains[td.chain];
     const rsv_theta th = A.theta[td.chain];
@@ -230,23 +246,37 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const R* y2 = A.y2 + cd.d_off;
     const R* lr = A.lrv + cd.d_off;
     const R* msq_tab = MASS ? A.mass_sqrt + cd.d_off : nullptr;
+    constexpr int ROW = Stage<R, S, NW, (NW == 1 ? 4 : 1)>::row;
+    const int g = wv * kWave + lane;
+    const int wbase = td.la + wv * kWave * S;  // the wavefront's block of 64 S sites
+    if constexpr (STAGE) {
+        // coalesced rounds; the values go to their owners through LDS below
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int t = t0 + j;
-        const bool live = t < T;
-        h[j] = live ? state_at(hc, t, shift) : R(0);
-        if constexpr (MASS) msq[j] = live ? msq_tab[t] : R(1);
-        y_in[j] = live ? y2[t] : R(0);
-        r_in[j] = live ? lr[t] : R(0);
+        for (int r = 0; r < S; ++r) {
+            const int t = wbase + r * kWave + lane;
+            const bool live = t < T;
+            h[r] = live ? state_at(hc, t, shift) : R(0);
+            y_in[r] = live ? y2[t] : R(0);
+            r_in[r] = live ? lr[t] : R(0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int t = t0 + j;
+            const bool live = t < T;
+            h[j] = live ? state_at(hc, t, shift) : R(0);
+            y_in[j] = live ? y2[t] : R(0);
+            r_in[j] = live ? lr[t] : R(0);
+        }
+    }
+    if constexpr (MASS) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) msq[j] = (t0 + j < T) ? msq_tab[t0 + j] : R(1);
     }
     // batch-means accumulators of the starting state (the previous sweep's
     // result) and the trace row of the previous sweep, on the exact sites,
-    // read here and written back below.  They need no per-lane order, so the
-    // wavefront covers its block of 64 S sites in coalesced rounds (round r:
-    // site wbase + 64 r + lane) instead of each lane's S neighbouring sites
-    // (addresses S elements apart across lanes, which cost the memory pipeline
-    // several times more per element); the state values are read again the same way.
-    const int wbase = td.la + wv * kWave * S;
+    // read here and written back below, in the same coalesced rounds (they
+    // need no per-lane order; without the stage the state is read again)
     const bool acc_on = A.acc_sum || A.acc_sq || A.h_prev_out;
     if (acc_on) {
 #pragma unroll
@@ -254,7 +284,10 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
             const int t = wbase + r * kWave + lane;
             const int64_t i = cd.h_off + t;
             const bool ex = t >= td.a && t < td.b;
-            acc_h[r] = ex ? state_at(hc, t, shift) : R(0);
+            if constexpr (STAGE)
+                acc_h[r] = h[r];
+            else
+                acc_h[r] = ex ? state_at(hc, t, shift) : R(0);
             acc_s[r] = (ex && A.acc_sum) ? A.acc_sum[i] : 0.0f;
             acc_q[r] = (ex && A.acc_sq) ? A.acc_sq[i] : 0.0f;
         }
@@ -289,19 +322,31 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         }
     }
 
+    if constexpr (STAGE) {
+        // round r, lane l held site offset o = 64 r + l of the wavefront's
+        // block: lane o / S's site o % S
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const int o = r * kWave + lane;
+            const int slot = (o % S) * ROW + wv * kWave + o / S;
+            stage[0 * S * ROW + slot] = h[r];
+            stage[1 * S * ROW + slot] = y_in[r];
+            stage[2 * S * ROW + slot] = r_in[r];
+        }
+        wave_sync_lds();
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            h[j] = stage[(0 * S + j) * ROW + g];
+            y_in[j] = stage[(1 * S + j) * ROW + g];
+            r_in[j] = stage[(2 * S + j) * ROW + g];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const double yy = static_cast<double>(y_in[j]);
         const double rr = static_cast<double>(r_in[j]);
         dc[j] = static_cast<R>(-dk * (c_base - rr * inv_su));
         ds[j] = RET ? static_cast<R>(0.5 * dk * yy) : R(0);
-        if constexpr (STAGE) {
-            constexpr int NT = 64 * NW;
-            const int g = wv * kWave + lane;
-            stage[(0 * S + j) * NT + g] = static_cast<double>(h[j]);
-            stage[(1 * S + j) * NT + g] = yy;
-            stage[(2 * S + j) * NT + g] = rr;
-        }
     }
     // a non-finite value in the current state (written by the caller, since
     // accepted proposals always have a finite dH) or in theta is flagged for
@@ -501,14 +546,14 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     //      sufficient statistics of the proposal and of the current state ----
     const double* y2d = A.y2_d + cd.d_off;
     const double* lrd = A.lrv_d + cd.d_off;
-    constexpr int NTS = 64 * NW;
-    const int gl = wv * kWave + lane;
+    // FP64 keeps y^2 and ln RV in the stage; FP32 reads them in FP64 from memory
+    constexpr bool STAGE_DATA = STAGE && sizeof(R) == sizeof(double);
     double h0d[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         if constexpr (STAGE)
-            h0d[j] = stage[(0 * S + j) * NTS + gl];  // 0 beyond T, as below
+            h0d[j] = static_cast<double>(stage[(0 * S + j) * ROW + g]);  // 0 beyond T, as below
         else
             h0d[j] = (t < T) ? static_cast<double>(state_at(hc, t, shift)) : 0.0;
     }
@@ -542,8 +587,8 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const int t = t0 + j;
         if (t < td.a || t >= td.b) continue;
         const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
-        const double rr = STAGE ? stage[(2 * S + j) * NTS + gl] : lrd[t];
-        const double yy = RET ? (STAGE ? stage[(1 * S + j) * NTS + gl] : y2d[t]) : 0.0;
+        const double rr = STAGE_DATA ? static_cast<double>(stage[(2 * S + j) * ROW + g]) : lrd[t];
+        const double yy = RET ? (STAGE_DATA ? static_cast<double>(stage[(1 * S + j) * ROW + g]) : y2d[t]) : 0.0;
         const double h1n = (j == S - 1) ? h1_up : static_cast<double>(h[j + (j < S - 1)]);
         const double h0n = (j == S - 1) ? h0_up : h0d[j + (j < S - 1)];
         double a1, a0;
@@ -604,7 +649,7 @@ __device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
     constexpr int kTilesPerBlock = NW == 1 ? 4 : 1;
     using St = Stage<R, S, NW, kTilesPerBlock>;
     __shared__ TileShared<R, NW> sh_all[kTilesPerBlock];
-    __shared__ double stage_all[kTilesPerBlock][St::n];
+    __shared__ R stage_all[kTilesPerBlock][St::n];
     const int lane = threadIdx.x & (kWave - 1);
     // wavefront index in the block: uniform, so the tile index and everything
     // read through it stay in scalar registers
@@ -612,7 +657,7 @@ __device__ __forceinline__ void traj_launch_body(const TrajArgs<R>& A) {
     const int w = blockIdx.x * kTilesPerBlock + wv_blk / NW;
     if (w >= A.n_list) return;  // uniform over the tile's wavefronts
     const int tile_id = A.tile_first + w;
-    double* stage = stage_all[wv_blk / NW];
+    R* stage = stage_all[wv_blk / NW];
     if (A.tiles[tile_id].edge)
         traj_tile<R, S, NW, MASS, true, RET, St::on>(A, sh_all[wv_blk / NW], tile_id,
                                                      wv_blk % NW, lane, stage);
