@@ -652,6 +652,27 @@ def test_tile_shapes_give_the_same_trajectory():
         np.testing.assert_array_equal(o, outs[0])
 
 
+def test_fp32_tile_shapes_agree():
+    """FP32-mixed: h after a trajectory is bitwise equal across tile shapes
+    (the FP32 loop's arithmetic does not depend on the tiling), and dH agrees
+    to rounding (its tile partials are grouped by the tiling), over enough
+    tiles (800 000 sites) that the wavefronts of a tile run at different
+    paces: the tile's LDS stage is shared by them."""
+    k, dt = 30, 0.03
+    outs = []
+    for S, NW in [(8, 1), (8, 2), (8, 4), (8, 8), (16, 1), (16, 2), (16, 4)]:
+        smp, offsets, ys, rs, h0, th = sampler([200000, 200000], 2, k=k, S=S, NW=NW,
+                                               precision=RSV_F32_MIXED)
+        p0 = np.random.default_rng(3).standard_normal(h0.size)
+        dh, acc = smp.trajectory(1, (k, dt), p0=p0, log_u=np.full(smp.n_chains, -1e9))
+        outs.append((smp.h.cpu().numpy(), dh.cpu().numpy(), acc.cpu().numpy()))
+        smp.close()
+    for h, dh, acc in outs:  # every finite dH is accepted at ln u = -1e9
+        assert np.all(np.isfinite(dh)) and bool(acc.all())
+        np.testing.assert_array_equal(h, outs[0][0])
+        np.testing.assert_allclose(dh, outs[0][1], rtol=1e-9, atol=1e-9)
+
+
 @pytest.mark.parametrize("S,NW,k,dt", [(4, 1, 123, 0.004), (8, 1, 251, 0.002), (8, 4, 1, 0.3),
                                        (4, 4, 2, 0.2)])
 def test_extreme_step_counts(S, NW, k, dt):
