@@ -193,11 +193,12 @@ __device__ __forceinline__ void sincos_2pi_f32(float u, float& sn, float& cs) {
     cs = ((q + 1) & 2) ? -c_sel : c_sel;
 }
 
-// 2^{-g} in FP32 by the hardware base-2 exponential: e^{-h} of the leapfrog
-// force for the FP32 path's position variable g = h log2 e.  Holding g
-// instead of h changes the force by a relative |h| 2^-24 or so, the same as
-// rounding h itself to FP32 does; the force may be any function of position
-// (the chain stays exact, dH is formed in FP64 from h).
-__device__ __forceinline__ float exp2_neg(float g) { return __builtin_amdgcn_exp2f(-g); }
+// e^x in FP32 for the leapfrog force: 2^(x log2 e) by the hardware base-2
+// exponential.  Rounding x log2 e to FP32 changes the value by a relative
+// |x| 2^-24 or so, the same as rounding h itself to FP32 does; the force may
+// be any function of position (the chain stays exact, dH is formed in FP64).
+__device__ __forceinline__ float exp_force(float x) {
+    return __builtin_amdgcn_exp2f(x * 0x1.715476p+0f);
+}
 
 }  // namespace rsv

@@ -31,20 +31,12 @@ __device__ inline R ghost_neighbour(R h, R mu, R phi) {
     return mu + phi * (h - mu);
 }
 
-// The FP32 leapfrog runs on the scaled position g = h log2 e (kPosScale), so
-// that the force's e^{-h} is the hardware 2^{-g}; the stencil and drift
-// constants carry the scale, and h = g ln 2 is restored after the loop.  The
-// FP64 leapfrog runs on h itself.
-template <typename R>
-constexpr double kPosScale = sizeof(R) == sizeof(float) ? 1.4426950408889634 : 1.0;
-
-// e^{-h} of the force, from the leapfrog's position variable x (h, or g in FP32).
 template <typename R>
 __device__ inline R exp_neg(R x);
 template <>
 __device__ inline double exp_neg<double>(double x) { return exp_force(-x); }
 template <>
-__device__ inline float exp_neg<float>(float x) { return exp2_neg(x); }
+__device__ inline float exp_neg<float>(float x) { return exp_force(-x); }
 
 // Value of the current state at a site: the stored entry plus the chain's
 // pending level shift (0 unless level moves are on), rounded to the state's
@@ -77,8 +69,7 @@ __device__ inline double step_size(uint64_t seed, uint64_t sweep, uint64_t chain
 // One site of a momentum step (kick) p += dk g(h) of eqs. (6)-(8): with the
 // per-site constants dc = -dk (c_base - r/sigma_u^2) and ds = dk y^2 / 2 and
 // the per-chain mda = -dk alpha, db = dk beta, the force term is
-// dc + mda h + db (h_l + h_r) + ds e^{-h}.  In FP32 the position arguments
-// are g = h log2 e and mda, db arrive divided by log2 e.
+// dc + mda h + db (h_l + h_r) + ds e^{-h}.
 template <typename R, bool RET>
 __device__ __forceinline__ R kick_site(R p, R dc, R ds, R mda, R db, R h, R hl, R hr) {
     R acc = p + dc;
@@ -223,11 +214,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     const double alpha = (1.0 + phi * phi) * inv_se + inv_su;
     const double beta = phi * inv_se;
     const double c_base = (RET ? 0.5 : 0.0) + xi * inv_su - mu * (1.0 - phi) * (1.0 - phi) * inv_se;
-    // constants of the leapfrog's position variable (h, or g = h log2 e in FP32)
-    constexpr double kS = kPosScale<R>;
-    const R mda = static_cast<R>(-dk * alpha / kS);
-    const R db = static_cast<R>(dk * beta / kS);
-    const R mu_r = static_cast<R>(mu * kS), phi_r = static_cast<R>(phi);
+    const R mda = static_cast<R>(-dk * alpha);
+    const R db = static_cast<R>(dk * beta);
+    const R mu_r = static_cast<R>(mu), phi_r = static_cast<R>(phi);
 
     // The loads of the tile's inputs are issued first and consumed after the
     // momentum draw, which needs none of them, so that their latency overlaps
@@ -377,16 +366,11 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
     for (int j = 0; j < S; ++j) {
         const int t = t0 + j;
         const double im = MASS ? inv_mass(msq[MASS ? j : 0]) : 1.0;
-        if constexpr (MASS) dtm[j] = static_cast<R>(dt * im * kS);
+        if constexpr (MASS) dtm[j] = static_cast<R>(dt * im);
         if (t >= td.a && t < td.b) {
             const double pj = static_cast<double>(p[j]);
             kin0 += 0.5 * pj * pj * im;
         }
-    }
-
-    if constexpr (kS != 1.0) {
-#pragma unroll
-        for (int j = 0; j < S; ++j) h[j] *= static_cast<R>(kS);
     }
 
     // ---- integrator: the leapfrog of eqs. (6)-(8), Omelyan's or Forest-Ruth's ----
@@ -454,9 +438,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         constexpr double f_first = OM ? kLambda : 0.5;
         constexpr double f_even = OM ? 1.0 - 2.0 * kLambda : 1.0;
         constexpr double f_odd = OM ? 2.0 * kLambda : 1.0;
-        const R s_first = wave_uniform(static_cast<R>(f_first * dt * kS));
-        const R s_even = wave_uniform(static_cast<R>(f_even * dt * kS));
-        const R s_odd = wave_uniform(static_cast<R>(f_odd * dt * kS));
+        const R s_first = wave_uniform(static_cast<R>(f_first * dt));
+        const R s_even = wave_uniform(static_cast<R>(f_even * dt));
+        const R s_odd = wave_uniform(static_cast<R>(f_odd * dt));
         // h += c p (identity mass: c = f dt; diagonal mass: c = f dt / m_t)
         auto drift = [&](auto which_c) {
             constexpr int which = decltype(which_c)::value;  // 0 first/last, 1 even, 2 odd
@@ -500,9 +484,9 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         const R f_half = wave_uniform(static_cast<R>(0.5 * kTheta));
         const R f_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta)));
         const R f_full = wave_uniform(static_cast<R>(kTheta));
-        const R c_half = wave_uniform(static_cast<R>(0.5 * kTheta * dt * kS));
-        const R c_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta) * dt * kS));
-        const R c_full = wave_uniform(static_cast<R>(kTheta * dt * kS));
+        const R c_half = wave_uniform(static_cast<R>(0.5 * kTheta * dt));
+        const R c_mid = wave_uniform(static_cast<R>(0.5 * (1.0 - kTheta) * dt));
+        const R c_full = wave_uniform(static_cast<R>(kTheta * dt));
         // h += c p: c = f dt (identity mass) or f dt / m_t
         auto drift_by = [&](R f, R c) {
 #pragma unroll
@@ -537,10 +521,6 @@ __device__ __forceinline__ void traj_tile(const TrajArgs<R>& A, TileShared<R, NW
         integrate_fr();
     else
         integrate(std::false_type{});
-    if constexpr (kS != 1.0) {  // back to h = g ln 2 (the stored proposal)
-#pragma unroll
-        for (int j = 0; j < S; ++j) h[j] *= static_cast<R>(1.0 / kS);
-    }
 
     // ---- dH = sum over exact sites of per-site differences (FP64), and the
     //      sufficient statistics of the proposal and of the current state ----
