@@ -145,3 +145,36 @@ def test_mass_layout_fp64_sampled_chains():
                 assert bool(acc[c]) == ref["accepted"], (s, j)
                 assert np.max(np.abs(h_gpu[sl] - ref["h"])) <= 1e-12 * max(1.0, np.abs(ref["h"]).max())
     smp.close()
+
+
+def test_fp32_dh_error_has_no_coherent_bias():
+    """FP32-mixed against FP64 from the same state, momenta and ln u at
+    T = 2^20 (k = 50, dtau 0.05 (1000 / T)^(1/4)), after 20 sweeps from the
+    simulated path: each FP32 rounding perturbs a site's contribution to dH
+    independently, so |dH_FP32 - dH_FP64| grows like sqrt(T) (median 2.8e-3
+    at T = 2^22 in the precision study, so ~1.4e-3 here); a coherent relative
+    shift eps of every h_t would add about eps * T (1e-8 gives 1e-2 here).
+    Bounds: median over 8 trajectories <= 4e-3, maximum <= 1.2e-2."""
+    T, k = 1 << 20, 50
+    dt = 0.05 * (1000.0 / T) ** 0.25
+    th = dict(synth.THETA_STAR)
+    y, r, h = synth.simulate_rsv_long(T, th, 2)
+    s32 = api.RSVSampler([0, T], y, r, h, th, max_steps=k, seed=2, precision=RSV_F32_MIXED)
+    s64 = api.RSVSampler([0, T], y, r, h.astype(np.float32).astype(np.float64), th,
+                         max_steps=k, seed=2, precision=RSV_F64)
+    s32.sweep(0, 20, (k, dt), update_theta=True, record=())
+    err = []
+    for i in range(8):
+        sweep = 500 + i
+        s64.h.copy_(s32.h.to(torch.float64))
+        s64.theta.copy_(s32.theta)
+        p0 = s64.momenta(sweep).to(torch.float32).to(torch.float64)
+        lu = [-1e9]
+        da, _ = s32.trajectory(sweep, (k, dt), p0=p0, log_u=lu)
+        db, _ = s64.trajectory(sweep, (k, dt), p0=p0, log_u=lu)
+        err.append(abs(float(da.item()) - float(db.item())))
+    print(f"|dH_FP32 - dH_FP64| at T = 2^20: {np.round(err, 5)}")
+    assert np.median(err) <= 4e-3
+    assert max(err) <= 1.2e-2
+    s32.close()
+    s64.close()
