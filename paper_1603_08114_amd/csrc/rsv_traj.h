@@ -1146,7 +1146,10 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     static_assert(NT == 256 && kSliceTiles * kPart % NT == 0, "slice layout");
     constexpr int kLoads = kSliceTiles * kPart / NT;
+    constexpr int kMergeChunk = 32;  // slices per chunk of the final merge
+    constexpr int kMergeLoads = (kMergeChunk * 2 * kNQ + kWave - 1) / kWave;
     __shared__ Comp part[NT / kWave][kNQ];
+    __shared__ double merge_buf[kMergeLoads * kWave];
     __shared__ ThetaDraws draws;
     __shared__ int last;
     const int c = A.chain_first + static_cast<int>(blockIdx.y);
@@ -1201,12 +1204,35 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     __threadfence();
     if (tid == 0) A.arrive[c] = 0u;  // for the next launch
     const double* first = A.slices + (static_cast<int64_t>(c) + cd.tile_begin / kSliceTiles) * (2 * kNQ);
-    if (tid < kNQ) {
-        Comp m{first[2 * tid], first[2 * tid + 1]};
-        for (int s = 1; s < n_sl; ++s)
-            m = comp_merge(m, Comp{first[s * 2 * kNQ + 2 * tid], first[s * 2 * kNQ + 2 * tid + 1]});
-        if (cd.edge_tile >= 0) comp_add(m, A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + tid]);
-        part[0][tid] = m;
+    if (tid < kWave) {
+        // the first wavefront loads the slices kMergeChunk at a time (all of
+        // a chunk's loads in flight together) into LDS, then lanes 0..kNQ-1
+        // merge them in slice order
+        const bool has_edge = tid < kNQ && cd.edge_tile >= 0;
+        const double e = has_edge ? A.partials[static_cast<int64_t>(cd.edge_tile) * kPart + tid] : 0.0;
+        Comp m{0.0, 0.0};
+        for (int s0 = 0; s0 < n_sl; s0 += kMergeChunk) {
+            const int ns = min(kMergeChunk, n_sl - s0);
+            const double* src = first + static_cast<int64_t>(s0) * (2 * kNQ);
+            double v[kMergeLoads];
+#pragma unroll
+            for (int j = 0; j < kMergeLoads; ++j) {
+                const int i = tid + kWave * j;
+                v[j] = i < ns * 2 * kNQ ? src[i] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kMergeLoads; ++j) merge_buf[tid + kWave * j] = v[j];
+            wave_sync_lds();
+            if (tid < kNQ) {
+                for (int s = 0; s < ns; ++s) {
+                    const Comp x{merge_buf[s * 2 * kNQ + 2 * tid], merge_buf[s * 2 * kNQ + 2 * tid + 1]};
+                    m = s0 + s == 0 ? x : comp_merge(m, x);
+                }
+            }
+            wave_sync_lds();
+        }
+        if (has_edge) comp_add(m, e);
+        if (tid < kNQ) part[0][tid] = m;
     }
     // the random numbers by the other wavefronts, while the first merges
     if (tid >= kWave) finalize_draws(A, c, cd.T, tid - kWave, NT - kWave, draws);
