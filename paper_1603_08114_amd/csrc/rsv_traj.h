@@ -918,13 +918,36 @@ struct Decision {
     double shift;   // the chain's pending level shift after this sweep
 };
 
+// What the decision reads of chain c besides its totals: the edge values,
+// the pending level shift of the current state, the caller's ln u (if given)
+// and theta.  Loaded by the deciding lane before the reductions, so that
+// their memory latency overlaps them.
+struct ChainIn {
+    double edge[kEdge];
+    double shift;
+    double log_u;
+    rsv_theta th;
+};
+
+__device__ __forceinline__ ChainIn load_chain_in(const FinalizeArgs& A, const int c) {
+    ChainIn in;
+    const double* ce = A.chain_edge + static_cast<int64_t>(c) * kEdge;
+#pragma unroll
+    for (int q = 0; q < kEdge; ++q) in.edge[q] = ce[q];
+    in.shift = A.shift ? A.shift[c] : 0.0;
+    in.log_u = A.log_u ? A.log_u[c] : 0.0;
+    in.th = A.theta[c];
+    return in;
+}
+
 // Metropolis test, statistics and theta update of chain c from its totals
-// tot[kNQ] (dH, statistics of h' and h, S of h' and h) and edge values
-// edge[kEdge], by one lane.  shift_in is the pending level shift of the
-// current state.  Writes theta, the per-chain outputs and counters of A.
+// tot[kNQ] (dH, statistics of h' and h, S of h' and h) and what load_chain_in
+// read, by one lane.  Writes theta, the per-chain outputs and counters of A.
 __device__ Decision finalize_decide(const FinalizeArgs& A, const int c, const int T,
-                                    const double (&tot)[kNQ], const double (&edge)[kEdge],
-                                    double shift_in, ThetaDraws& draws) {
+                                    const double (&tot)[kNQ], const ChainIn& in,
+                                    ThetaDraws& draws) {
+    const double (&edge)[kEdge] = in.edge;
+    const double shift_in = in.shift;
     // a Gamma draw whose parallel attempts were all rejected continues serially
     // up to its first accepted attempt, so the first accepted attempt is the
     // same one a fully parallel evaluation would find
@@ -944,12 +967,12 @@ __device__ Decision finalize_decide(const FinalizeArgs& A, const int c, const in
             }
         }
     }
-    const rsv_theta th = A.theta[c];
+    const rsv_theta th = in.th;
     bool use_prop = false;
     if (A.do_metropolis) {
 #pragma clang fp contract(off)
         const double dH = tot[kPartDH];
-        const double lu = A.log_u ? A.log_u[c] : draws.log_u_accept;
+        const double lu = A.log_u ? in.log_u : draws.log_u_accept;
         const bool finite = isfinite(dH);
         const bool accept = finite && (lu < -dH);
         if (!finite) atomicAdd(&A.counters[kCntNonfiniteDH], 1u);
@@ -1000,14 +1023,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Chain c's decision from its totals, by one lane: edge values, the pending
-// shift, finalize_decide, then the state selector and the shift.
+// Chain c's decision from its totals, by one lane: finalize_decide, then the
+// state selector and the shift.
 __device__ __forceinline__ void finalize_commit(const FinalizeArgs& A, const int c, const int T,
-                                                const double (&tot)[kNQ], ThetaDraws& draws) {
-    const double* ce = A.chain_edge + static_cast<int64_t>(c) * kEdge;
-    const double edge[kEdge] = {ce[0], ce[1], ce[2], ce[3]};
-    const double shift_in = A.shift ? A.shift[c] : 0.0;
-    const Decision d = finalize_decide(A, c, T, tot, edge, shift_in, draws);
+                                                const double (&tot)[kNQ], const ChainIn& in,
+                                                ThetaDraws& draws) {
+    const Decision d = finalize_decide(A, c, T, tot, in, draws);
     if (d.accepted) A.state_sel[c] ^= 1;
     if (A.shift) A.shift[c] = d.shift;
 }
@@ -1026,6 +1047,8 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
     const ChainDesc cd = A.chains[c];
+    ChainIn in;
+    if (tid == 0) in = load_chain_in(A, c);
 
     const double* chain_parts = A.partials + static_cast<int64_t>(cd.tile_begin) * kPart;
     if constexpr (NT == kWave) {
@@ -1131,7 +1154,7 @@ __device__ void finalize_chain(const FinalizeArgs& A, const int c, Comp (&part)[
         for (int w = 1; w < NW; ++w) r = comp_merge(r, part[w][q]);
         tot[q] = r.s + r.c;
     }
-    finalize_commit(A, c, cd.T, tot, draws);
+    finalize_commit(A, c, cd.T, tot, in, draws);
 }
 
 // The split finalize of chains of many tiles: block (s, c) adds slice s
@@ -1202,7 +1225,11 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     __syncthreads();
     if (!last) return;
     __threadfence();
-    if (tid == 0) A.arrive[c] = 0u;  // for the next launch
+    ChainIn in;
+    if (tid == 0) {
+        A.arrive[c] = 0u;  // for the next launch
+        in = load_chain_in(A, c);
+    }
     const double* first = A.slices + (static_cast<int64_t>(c) + cd.tile_begin / kSliceTiles) * (2 * kNQ);
     if (tid < kWave) {
         // the first wavefront loads the slices kMergeChunk at a time (all of
@@ -1241,7 +1268,7 @@ __global__ __launch_bounds__(NT) void k_finalize_split(FinalizeArgs A) {
     double tot[kNQ];
 #pragma unroll
     for (int k = 0; k < kNQ; ++k) tot[k] = part[0][k].s + part[0][k].c;
-    finalize_commit(A, c, cd.T, tot, draws);
+    finalize_commit(A, c, cd.T, tot, in, draws);
 }
 
 // One chain per block of two wavefronts: the first loads and adds the tile
