@@ -12,6 +12,9 @@
   chains, T ~ U{1000..16000}, FP64, diagonal mass, tile (4, 4)): sampled
   chains (shortest, median, longest, plus a few seeded ones) against the
   oracle run on that chain alone.
+* Several long FP64 chains in the split finalize (one with more slices than
+  its final merge takes at once), three sweeps with the theta update, against
+  the oracle run of each chain.
 """
 import numpy as np
 import pytest
@@ -178,3 +181,54 @@ def test_fp32_dh_error_has_no_coherent_bias():
     assert max(err) <= 1.2e-2
     s32.close()
     s64.close()
+
+
+def test_split_finalize_several_long_chains_fp64():
+    """Several chains each in the split finalize (more than 128 tiles), one of
+    them with more slices (34) than the final merge takes at once (32): three
+    series (T = 1 000 000, 70 000, 20 000) x 2 chains, FP64, tile (4, 1), k =
+    10, three sweeps with the theta update, against the oracle run of each
+    chain alone (dH abs <= 1e-9 relative to max(1, |dH|), the accept
+    decisions and theta after every sweep rel <= 1e-10, the final h rel <=
+    1e-12; a chain stops being compared at a near-tie of its Metropolis
+    test)."""
+    Ts, C, k, seed, first = [1_000_000, 70_000, 20_000], 2, 10, 5, 7
+    th = dict(synth.THETA_STAR)
+    ys, rs, hs = [], [], []
+    for i, T in enumerate(Ts):
+        y, r, h = synth.simulate_rsv_long(T, th, 20 + i)
+        ys.append(y); rs.append(r); hs.append(h)
+    off = np.concatenate([[0], np.cumsum(Ts)])
+    h0 = np.concatenate([np.tile(hs[s], C) for s in range(len(Ts))])
+    dts = [0.05 * (1000.0 / T) ** 0.25 for T in Ts]
+    smp = api.RSVSampler(off, np.concatenate(ys), np.concatenate(rs), h0,
+                         [th] * (len(Ts) * C), chains_per_series=C, precision=RSV_F64,
+                         max_steps=k, seed=seed, sites_per_lane=4, waves_per_tile=1)
+    n = 3
+    out = smp.sweep(first, n, [(k, d) for d in dts], record=("delta_h", "accepted", "theta"))
+    dh = out["delta_h"].cpu().numpy()
+    acc = out["accepted"].cpu().numpy().astype(bool)
+    tht = out["theta"].cpu().numpy()
+    h_gpu = smp.h.cpu().numpy()
+    smp.close()
+    compared = 0
+    for s, T in enumerate(Ts):
+        for j in range(C):
+            c = s * C + j
+            ref = oracle.run(hs[s], th, ys[s] ** 2, rs[s], k, dts[s], n, seed=seed, chain=c,
+                             first_sweep=first)
+            tie = False
+            for i in range(n):
+                assert abs(dh[i, c] - ref["dH"][i]) <= 1e-9 * max(1.0, abs(ref["dH"][i])), (c, i)
+                if abs(ref["dH"][i] + oracle.log_u(seed, first + i, c)) <= 1e-9:
+                    tie = True
+                    break
+                assert acc[i, c] == ref["accepted"][i], (c, i)
+                np.testing.assert_allclose(tht[i, c], ref["theta_trace"][i], rtol=1e-10,
+                                           atol=1e-13, err_msg=f"chain {c} sweep {i}")
+                compared += 1
+            if not tie:
+                a = C * int(off[s]) + j * T
+                scale = max(1.0, np.max(np.abs(ref["h"])))
+                assert np.max(np.abs(h_gpu[a:a + T] - ref["h"])) <= 1e-12 * scale, c
+    assert acc.any() and compared >= n * len(Ts) * C - 2
