@@ -30,17 +30,19 @@ VARIANTS = {("f64", 4, 1): "IdLi4ELi1ELb1E", ("f64", 4, 2): "IdLi4ELi2ELb1E",
 
 
 def assemble() -> str:
-    text = []
+    srcs = ("rsv_traj_f64.hip", "rsv_traj_f32.hip")
     with tempfile.TemporaryDirectory() as d:
-        for src in ("rsv_traj_f64.hip", "rsv_traj_f32.hip"):
-            out = os.path.join(d, src + ".s")
-            cmd = ["hipcc", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
-                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                   "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC, "--cuda-device-only",
-                   "-S", os.path.join(B.CSRC, src), "-o", out]
-            subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL)
-            text.append(open(out).read())
-    return "\n".join(text)
+        outs = [os.path.join(d, src + ".s") for src in srcs]
+        procs = [subprocess.Popen(["hipcc", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
+                                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                                   "-I", os.path.join(B.ROOT, "include"), "-I", B.CSRC,
+                                   "--cuda-device-only", "-S", os.path.join(B.CSRC, src),
+                                   "-o", out], stderr=subprocess.DEVNULL)
+                 for src, out in zip(srcs, outs)]
+        for p, src in zip(procs, srcs):
+            if p.wait() != 0:
+                raise RuntimeError(f"hipcc failed on {src}")
+        return "\n".join(open(out).read() for out in outs)
 
 
 def kernel_text(asm: str, tag: str) -> str:
